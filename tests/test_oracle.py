@@ -1,0 +1,235 @@
+"""Pins for the CPU oracle: hand-derived answers, the paper's printed worked example and
+byte accounting, closed forms, a library routine for overlapping occurrences, and
+cross-checks between independently written algorithms. Planted mistakes (in copies of
+the oracle, never in the product) show that each pin bites."""
+import itertools
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import literal, native, trie
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _cases():
+    return [(c["name"], c["alphabet"], [bytes.fromhex(p) for p in c["patterns"]],
+             bytes.fromhex(c["text"]), [tuple(x) for x in c["expected"]])
+            for c in _load("hand_cases.json")["cases"]]
+
+
+def _pairs(keys):
+    return [(int(k) >> 32, int(k) & 0xFFFFFFFF) for k in keys]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    native.build(force=False)
+
+
+# ----------------------------------------------------------------------------- hand cases
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
+def test_hand_cases_all_oracles(case):
+    name, alphabet, pats, text, expected = case
+    assert literal.match_set(pats, text) == expected
+    assert _pairs(native.brute(pats, text)) == expected
+    assert _pairs(native.AhoCorasick(pats, alphabet).scan(text)) == expected
+    assert trie.walk_matches(pats, alphabet, text) == expected
+
+
+def test_overlapping_occurrences_via_regex_lookahead():
+    """``re`` with a zero-width lookahead finds every (overlapping) occurrence of one
+    pattern: a library routine the oracles did not use."""
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        sigma = int(rng.choice([2, 3, 4]))
+        pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(1, 5))).astype(np.uint8))
+                for _ in range(int(rng.integers(1, 6)))]
+        text = bytes(rng.integers(0, sigma, size=int(rng.integers(0, 80))).astype(np.uint8))
+        want = sorted((m.start(), j) for j, p in enumerate(pats)
+                      for m in re.finditer(b"(?=" + re.escape(p) + b")", text))
+        assert literal.match_set(pats, text) == want
+        assert _pairs(native.brute(pats, text)) == want
+        assert _pairs(native.AhoCorasick(pats, sigma).scan(text, chunk=7)) == want
+
+
+def test_closed_form_all_binary_texts():
+    """Over all 2^n binary texts, pattern p occurs (n - |p| + 1) * 2^(n - |p|) times in
+    total: each start position fixes |p| bits and leaves the rest free."""
+    pats = [b"\x00", b"\x01\x01", b"\x00\x01\x00", b"\x01\x01", b"\x01\x00\x01\x01"]
+    n = 9
+    want = sum((n - len(p) + 1) * 2 ** (n - len(p)) for p in pats if len(p) <= n)
+    ac = native.AhoCorasick(pats, 2)
+    got_ac = got_brute = 0
+    for bits in itertools.product((0, 1), repeat=n):
+        t = bytes(bits)
+        got_ac += len(ac.scan(t, chunk=4))
+        got_brute += len(native.brute(pats, t))
+    assert got_ac == want
+    assert got_brute == want
+
+
+def test_random_small_cross_check():
+    rng = np.random.default_rng(7)
+    for trial in range(300):
+        sigma = int(rng.choice([2, 4, 256]))
+        npat = int(rng.integers(1, 51))
+        pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(1, 9))).astype(np.uint8))
+                for _ in range(npat)]
+        n = int(rng.integers(0, 2001)) if trial % 10 == 0 else int(rng.integers(0, 200))
+        # text symbols sometimes exceed the alphabet (no transition)
+        hi = sigma + (1 if sigma < 256 and trial % 3 == 0 else 0)
+        text = bytes(rng.integers(0, hi, size=n).astype(np.uint8))
+        want = literal.match_set(pats, text)
+        assert _pairs(native.brute(pats, text)) == want
+        chunk = int(rng.integers(1, 64))
+        assert _pairs(native.AhoCorasick(pats, sigma).scan(text, chunk=chunk)) == want
+        if trial % 5 == 0:
+            assert trie.walk_matches(pats, sigma, text) == want
+
+
+def test_uniform_workload_brute_equals_ac_and_contains_plants():
+    from paper_1704_02272_amd import workloads as W
+    w = W.uniform_256()
+    b = native.brute(w.patterns, w.text)
+    a = native.AhoCorasick(w.patterns, 256).scan(w.text, chunk=1 << 16)
+    assert np.array_equal(a, b)
+    keys = set(int(k) for k in a)
+    t = w.text.tobytes()
+    surviving = {(off << 32) | j for off, j in w.plants
+                 if t[off:off + len(w.patterns[j])] == w.patterns[j]}
+    # every plant still spelled in the final text is reported
+    assert surviving <= keys
+    # uniform text: expected natural matches sum_j (n-|p|+1) 256^-|p| is far below 1
+    n = len(w.text)
+    expect_natural = sum((n - len(p) + 1) * 256.0 ** (-len(p)) for p in w.patterns)
+    assert expect_natural < 0.1
+    assert len(keys - surviving) <= 3
+
+
+# ------------------------------------------------------------------------- storage model
+def test_worked_example_section_3_1():
+    g = _load("worked_example_3_1.json")
+    pats = [p.encode() for p in g["patterns"]]
+    off, bm = trie.paper_layout(pats, g["alphabet"])
+    a = g["node_of_A"]
+    assert trie.canonical_nodes(pats)[a] == b"A"
+    assert [c for c in range(256) if (bm[a] >> c) & 1] == g["children_bits_of_A"]
+    assert off[a] == g["offset_of_A"]
+    assert trie.child(off, bm, a, ord("B")) == g["node_of_B"]
+    assert trie.popcount_below(bm[a], ord("D")) == g["popcount_below_D"]
+    assert trie.child(off, bm, a, ord("D")) == g["node_of_D"]
+    # the bitmap of 256 bits is 8 words of 32 bits; 'B' and 'D' sit in word 2
+    assert g["bitmap_words"] * g["bitmap_word_bits"] == 256
+    assert (66 // 32, 68 // 32) == (2, 2)
+
+
+def test_layout_is_breadth_first_queue_order():
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        sigma = int(rng.choice([2, 4, 26, 256]))
+        pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(1, 7))).astype(np.uint8))
+                for _ in range(int(rng.integers(1, 40)))]
+        assert trie.paper_layout(pats, sigma) == trie.bfs_queue_layout(pats, sigma)
+
+
+def test_layout_offsets_count_children():
+    """Breadth-first numbering: the first child of the k-th node that has children
+    comes right after the children of all earlier nodes, so
+    offset[k] = 1 + (sum of degrees of nodes before k); leaves keep offset 0."""
+    rng = np.random.default_rng(5)
+    pats = [bytes(rng.integers(0, 4, size=int(rng.integers(1, 9))).astype(np.uint8))
+            for _ in range(200)]
+    off, bm = trie.paper_layout(pats, 4)
+    deg = [bin(b).count("1") for b in bm]
+    run = 1
+    for k in range(len(off)):
+        if deg[k]:
+            assert off[k] == run
+        else:
+            assert off[k] == 0
+        run += deg[k]
+    assert run == len(off)  # every node but the root is somebody's child
+    # node count = 1 + number of distinct non-empty prefixes
+    prefixes = {p[:d] for p in pats for d in range(1, len(p) + 1)}
+    assert len(off) == 1 + len(prefixes)
+
+
+def test_memory_accounting_section_3_1():
+    g = _load("memory_accounting_3_1.json")
+    for sigma, b in g["bytes_per_node"].items():
+        assert trie.paper_node_bytes(int(sigma)) == b
+    mib = 1 << 20
+    t256, t32 = g["tries"]
+    size256 = trie.paper_table_bytes(t256["nodes"], 256) / mib
+    size32 = trie.paper_table_bytes(t32["nodes"], 32) / mib
+    assert int(size256 * 10) / 10 == t256["printed_mb"]
+    assert int(size32 * 10) / 10 == t32["printed_mb"]
+    assert round(t256["other_system_mb"] / t256["printed_mb"], 1) == t256["printed_ratio"]
+    for k, ratio in t32["printed_ratios"].items():
+        assert round(t32["other_systems_mb"][k] / t32["printed_mb"], 2) == ratio
+
+
+def test_global_final_node_count_eq_2():
+    """Eq. 2 on a set where every pattern ends in its own childless leaf (prefix-free,
+    no duplicates): merging all final nodes into one removes |P| - 1 nodes. Counted
+    here directly on the node set."""
+    rng = np.random.default_rng(9)
+    pats = set()
+    while len(pats) < 60:
+        pats.add(bytes(rng.integers(0, 4, size=6).astype(np.uint8)))  # equal length: prefix-free
+    pats = sorted(pats)
+    nodes = trie.canonical_nodes(pats)
+    leaves = [s for s in nodes if s in pats]
+    merged = len(nodes) - len(leaves) + 1
+    assert trie.global_final_nodes(len(nodes), len(pats)) == merged
+
+
+# ---------------------------------------------------------------------- planted mistakes
+def test_pins_catch_planted_mistakes_in_c_oracle(tmp_path):
+    cases = _cases()
+
+    def hand_ok(lib):
+        for name, alphabet, pats, text, expected in cases:
+            if _pairs(native.brute(pats, text, lib=lib)) != expected:
+                return False
+            if _pairs(native.AhoCorasick(pats, alphabet, lib=lib).scan(text)) != expected:
+                return False
+        return True
+
+    for define in ("ORC_MUTANT_BRUTE_END", "ORC_MUTANT_NO_DICT", "ORC_MUTANT_ROOT_FAIL"):
+        lib = native.build_mutant(define, str(tmp_path))
+        assert not hand_ok(lib), define
+    # a too-short chunk overlap only shows when a match crosses a chunk end
+    lib = native.build_mutant("ORC_MUTANT_SHORT_OVERLAP", str(tmp_path))
+    pats = [b"abcd"]
+    text = b"xxabcdxx"
+    assert _pairs(native.AhoCorasick(pats, 256, lib=lib).scan(text, chunk=3)) != \
+        literal.match_set(pats, text)
+
+
+def test_pins_catch_planted_mistakes_in_python_oracle(monkeypatch):
+    cases = _cases()
+
+    def off_by_one(patterns, text):  # stops one start early
+        text = bytes(text)
+        return [(s, j) for s in range(len(text) - 1) for j, p in enumerate(patterns)
+                if p and s + len(p) <= len(text) and text[s:s + len(p)] == p]
+
+    def popcount_inclusive(bitmap, c):  # counts bit c itself
+        return bin(bitmap & ((1 << (c + 1)) - 1)).count("1")
+
+    assert any(off_by_one(p, t) != e for _, _, p, t, e in cases)
+    monkeypatch.setattr(trie, "popcount_below", popcount_inclusive)
+    g = _load("worked_example_3_1.json")
+    pats = [p.encode() for p in g["patterns"]]
+    off, bm = trie.paper_layout(pats, 256)
+    assert trie.child(off, bm, 1, ord("D")) != g["node_of_D"]
