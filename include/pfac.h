@@ -1,0 +1,152 @@
+/*
+ * pfac.h -- C ABI of a failure-less Aho-Corasick matcher for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the parallel failure-less Aho-Corasick of Section 2.3 (every text
+ * position starts its own walk of a goto-only trie and stops at the first missing
+ * transition) over the compressed storage model of Section 3.1 (a breadth-first node
+ * array, each node a first-child offset plus a child bitmap, children found by the
+ * popcount rule of Eq. 1).
+ *
+ * Result definition. For patterns p_0..p_{N-1} (non-empty byte strings over the symbols
+ * 0..alphabet-1) and a text T of n bytes, the result is every pair (s, j) with
+ * s + |p_j| <= n and T[s .. s+|p_j|) == p_j (the problem of Section 2.2). Each pair is
+ * returned as the 64-bit key (s << 32) | j; keys are written in increasing order, so
+ * they are sorted by start, then by pattern id. Duplicate patterns are all reported;
+ * a pattern that is a prefix of another is reported wherever it occurs. A text byte
+ * >= alphabet has no transition and so takes part in no match.
+ *
+ * Conventions.
+ *  - Every function returns an int status: PFAC_OK (0) or a negative PFAC_E* code.
+ *    No function throws or aborts across this boundary.
+ *  - "d_" arguments are device pointers (HBM of the current HIP device, e.g. a torch
+ *    tensor's data_ptr()); "h_" arguments are host pointers. The library never frees
+ *    memory it did not allocate.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Device work
+ *    is enqueued on it in order.
+ *  - An automaton is immutable after pfac_build. Scans on different streams or threads
+ *    may share it; destroying it while work that uses it is still queued is undefined
+ *    (synchronize first).
+ */
+#ifndef PFAC_H
+#define PFAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#define PFAC_API __attribute__((visibility("default")))
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define PFAC_OK 0
+#define PFAC_EINVAL (-1)         /* null pointer, size or option out of range          */
+#define PFAC_EEMPTY_PATTERN (-2) /* a pattern of length 0 (it would match everywhere)   */
+#define PFAC_ESYMBOL (-3)        /* a pattern byte >= alphabet                          */
+#define PFAC_ETOO_LARGE (-4)     /* node or id count past 32-bit offsets, or n >= 2^32  */
+#define PFAC_ENOMEM (-5)         /* host or device allocation failed                    */
+#define PFAC_EHIP (-6)           /* a HIP runtime call failed                           */
+#define PFAC_ECAPACITY (-7)      /* more matches than the output holds (see scans)      */
+#define PFAC_ENODEVICE (-8)      /* no usable gfx950 device                             */
+#define PFAC_EFORMAT (-9)        /* serialized automaton is malformed or truncated      */
+#define PFAC_ETIMEOUT (-10)      /* a device-side bounded wait expired (internal error) */
+
+/* Human-readable name of a status code (static storage, never NULL). */
+PFAC_API const char *pfac_strerror(int status);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+PFAC_API int pfac_version(void);
+
+typedef struct pfac_automaton pfac_automaton;
+
+/* ------------------------------------------------------------------- building
+ * pfac_build -- build the compressed table (Section 3.1): patterns are sorted
+ * bytewise, inserted breadth-first, and every node is stored as a first-child offset
+ * plus a child bitmap; the child on symbol c is offset + popcount(bits below c) (Eq. 1).
+ *
+ *   pats[i], lens[i]  pattern i (pattern id = i); the bytes are copied, the caller may
+ *                     free them on return. n_pats may be 0 (every scan then returns no
+ *                     match).
+ *   alphabet          1..256; symbols are the raw byte values 0..alphabet-1.
+ *   out               receives the automaton; free with pfac_destroy.
+ *
+ * Errors: PFAC_EINVAL (out NULL, pats/lens NULL with n_pats > 0, alphabet outside
+ * 1..256), PFAC_EEMPTY_PATTERN, PFAC_ESYMBOL, PFAC_ETOO_LARGE (more than 2^31 - 1
+ * nodes or a pattern longer than 2^24 bytes), PFAC_ENOMEM. On error *out is NULL.
+ * Host only: needs no GPU. */
+PFAC_API int pfac_build(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
+               uint32_t alphabet, pfac_automaton **out);
+
+/* Same as pfac_build with the patterns packed back to back: pattern i is
+ * bytes[offsets[i] .. offsets[i+1]), offsets has n_pats + 1 entries. */
+PFAC_API int pfac_build_csr(const uint8_t *bytes, const uint64_t *offsets, uint32_t n_pats,
+                   uint32_t alphabet, pfac_automaton **out);
+
+/* Free the automaton and its device copies. NULL is a no-op. */
+PFAC_API void pfac_destroy(pfac_automaton *a);
+
+/* Sizes and shape of a built automaton. */
+typedef struct {
+    uint32_t alphabet;
+    uint32_t n_patterns;
+    uint32_t n_nodes;            /* 1 + number of distinct non-empty pattern prefixes  */
+    uint32_t n_terminal_nodes;   /* nodes where at least one pattern ends               */
+    uint32_t min_len, max_len;   /* pattern lengths (0 when n_patterns == 0)            */
+    uint32_t depth;              /* trie depth (= max_len)                              */
+    uint32_t node_layout;        /* 0: 8-byte node (alphabet <= 32), 1: wide node      */
+    uint64_t paper_table_bytes;  /* n_nodes * (4 + ceil(alphabet / 8)), Section 3.1    */
+    uint64_t device_table_bytes; /* node arrays + pattern-id lists as stored in HBM     */
+    uint32_t root_depth;         /* levels folded into the LDS-resident root image     */
+    uint32_t filter_k;           /* symbols in the LDS prefix filter key (0 = none)    */
+    uint32_t filter_log2_bits;   /* log2 of the filter's bit count (0 = none)          */
+    uint32_t lds_image_bytes;    /* root image + filter, copied to LDS per workgroup   */
+} pfac_table_info_t;
+
+PFAC_API int pfac_table_info(const pfac_automaton *a, pfac_table_info_t *out);
+
+/* Copy the table in the paper's own layout (Section 3.1): for node q,
+ * offsets[q] = index of its first child (0 for a node without children) and
+ * bitmaps[q * words + w] = bits 32w .. 32w+31 of its child bitmap (bit c = symbol c),
+ * with words = ceil(alphabet / 32). Capacities are in elements; PFAC_EINVAL if either
+ * is too small for n_nodes. */
+PFAC_API int pfac_export_paper_table(const pfac_automaton *a, uint32_t *offsets, uint64_t offsets_cap,
+                            uint32_t *bitmaps, uint64_t bitmaps_cap);
+
+/* Pattern ids ending at each node as CSR: ids of node q are ids[first[q] .. first[q+1]),
+ * ascending. first has n_nodes + 1 entries, ids n_patterns. */
+PFAC_API int pfac_export_outputs(const pfac_automaton *a, uint32_t *first, uint64_t first_cap,
+                        uint32_t *ids, uint64_t ids_cap);
+
+/* ------------------------------------------------------------------- device
+ * Copy the table to device `device` (HIP ordinal). Done implicitly by the first scan
+ * on a device; the copy stays resident until pfac_destroy. Errors: PFAC_ENODEVICE (no
+ * such device, or not gfx950), PFAC_ENOMEM, PFAC_EHIP. */
+PFAC_API int pfac_upload(pfac_automaton *a, int device);
+
+/* ------------------------------------------------------------------- scanning
+ * pfac_scan_async -- scan n bytes at d_text (device memory) and write the keys of all
+ * matches, sorted, to d_keys (device memory); write the number of matches to *d_count
+ * (device memory, one uint64). Only enqueues work on `stream`; results are valid once
+ * the stream has completed. When the count exceeds cap, at most cap keys are written,
+ * their content is unspecified, and *d_count still holds the full count: reallocate and
+ * scan again. n must be < 2^32 (PFAC_ETOO_LARGE otherwise). The first call on a stream
+ * allocates that stream's scratch (counters, tile states); later calls reuse it, and a
+ * call whose text needs more scratch first waits for the stream, then grows it.
+ * Concurrent calls on the same stream from different host threads are not supported.
+ * Errors: PFAC_EINVAL (automaton or d_count NULL, d_text NULL with n > 0, d_keys NULL
+ * with cap > 0), PFAC_ETOO_LARGE, PFAC_ENODEVICE, PFAC_ENOMEM, PFAC_EHIP. */
+PFAC_API int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t n,
+                             uint64_t *d_keys, uint64_t cap, uint64_t *d_count, void *stream);
+
+/* pfac_scan -- pfac_scan_async, then wait for `stream` and return the count in *h_count
+ * (host memory). Returns PFAC_ECAPACITY when the count exceeds cap (*h_count = the
+ * capacity needed; d_keys content unspecified). */
+PFAC_API int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
+                       uint64_t cap, uint64_t *h_count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFAC_H */

@@ -1,0 +1,235 @@
+// Host-side construction of the compressed trie (Section 3.1) and of the device images.
+//
+// Patterns are sorted bytewise (shorter first when one is a prefix of another, pattern
+// id breaking ties) and the trie is built breadth-first, level by level. Because the
+// patterns are sorted, the patterns under any trie node form one contiguous run of the
+// sorted order; a node is kept as that run, and its children are the maximal sub-runs
+// that agree on the next byte, taken in increasing byte order. Numbering nodes in the
+// order they are created is then the breadth-first order of Section 3.1, and the first
+// child of a node is simply the index its first sub-run receives (Eq. 1's offset).
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "../../include/pfac.h"
+#include "pfac_impl.h"
+
+namespace pfac {
+namespace {
+
+inline uint32_t popc64(uint64_t x) { return (uint32_t)__builtin_popcountll(x); }
+
+struct Run {
+    uint32_t lo, hi;  // range of the sorted pattern order
+};
+
+// Key of the first `d` symbols of p in the root image: lexicographic order, i.e. the
+// first symbol in the most significant position, `bits` bits per symbol.
+inline uint32_t root_key(const uint8_t *p, uint32_t d, uint32_t bits) {
+    uint32_t k = 0;
+    for (uint32_t i = 0; i < d; i++) k = (k << bits) | p[i];
+    return k;
+}
+
+// Key of the first k symbols of p in the prefix filter. Byte symbols: little-endian
+// bytes (symbol 0 in bits 0..7), which is how the kernels read four text bytes as one
+// 32-bit word. Two-bit symbols: first symbol most significant.
+inline uint32_t filter_key(const uint8_t *p, uint32_t k, bool pack2) {
+    uint32_t key = 0;
+    if (pack2) {
+        for (uint32_t i = 0; i < k; i++) key = (key << 2) | p[i];
+    } else {
+        for (uint32_t i = 0; i < k; i++) key |= (uint32_t)p[i] << (8 * i);
+    }
+    return key;
+}
+
+void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
+    DevTable &t = a->shape;
+    t.pack2 = a->alphabet <= 4 ? 1 : 0;
+    const uint32_t bits = t.pack2 ? 2 : 8;
+    if (a->n_pats == 0) {
+        t.root_depth = t.root_bits = t.root_base = 0;
+        t.filter_k = t.filter_log2 = 0;
+        t.lds_words = t.rank_word = t.filter_word = 0;
+        a->lds_image.clear();
+        return;
+    }
+    const uint32_t dmax = t.pack2 ? 8 : 2;
+    const uint32_t kmax = t.pack2 ? 16 : 4;
+    const uint32_t D = std::min(a->min_len, dmax);
+    const uint32_t K = std::min(a->min_len, kmax);
+    t.root_depth = D;
+    t.root_bits = D * bits;
+    t.root_base = a->depth_start[D];
+    const uint32_t root_nbits = 1u << t.root_bits;
+    const uint32_t root_words = std::max<uint32_t>(1, root_nbits / 32);
+    const uint32_t rank_entries = root_words;  // one u16 per 32-bit word
+    const uint32_t rank_words = (rank_entries + 1) / 2;
+    uint32_t flog2 = 0;
+    std::vector<uint32_t> fkeys;
+    if (K > D) {
+        fkeys.reserve(a->n_pats);
+        for (uint32_t j = 0; j < a->n_pats; j++) fkeys.push_back(filter_key(P[j], K, t.pack2));
+        std::sort(fkeys.begin(), fkeys.end());
+        fkeys.erase(std::unique(fkeys.begin(), fkeys.end()), fkeys.end());
+        // about 64 filter bits per distinct prefix, between 8 Kibit and 256 Kibit
+        uint64_t want = (uint64_t)fkeys.size() * 64;
+        flog2 = 13;
+        while (flog2 < 18 && (1ull << flog2) < want) flog2++;
+    }
+    t.filter_k = K > D ? K : 0;
+    t.filter_log2 = flog2;
+    t.rank_word = root_words;
+    t.filter_word = root_words + rank_words;
+    const uint32_t filter_words = flog2 ? (1u << flog2) / 32 : 0;
+    t.lds_words = t.filter_word + filter_words;
+    a->lds_image.assign(t.lds_words, 0);
+    uint32_t *img = a->lds_image.data();
+    for (uint32_t j = 0; j < a->n_pats; j++) {
+        uint32_t key = root_key(P[j], D, bits);
+        img[key >> 5] |= 1u << (key & 31);
+    }
+    uint16_t *rank = reinterpret_cast<uint16_t *>(img + t.rank_word);
+    uint32_t run = 0;
+    for (uint32_t w = 0; w < root_words; w++) {
+        rank[w] = (uint16_t)run;
+        run += (uint32_t)__builtin_popcount(img[w]);
+    }
+    // every depth-D node is a D-prefix of some pattern (D <= shortest length)
+    if (run != a->depth_start[D + 1] - a->depth_start[D]) throw std::bad_alloc();
+    uint32_t *filt = img + t.filter_word;
+    for (uint32_t key : fkeys) {
+        uint32_t b = filter_index(key, flog2);
+        filt[b >> 5] |= 1u << (b & 31);
+    }
+}
+
+}  // namespace
+
+int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
+                    uint32_t alphabet, pfac_automaton **out) {
+    if (!out) return PFAC_EINVAL;
+    *out = nullptr;
+    if (alphabet < 1 || alphabet > 256) return PFAC_EINVAL;
+    if (n_pats > 0 && (!pats || !lens)) return PFAC_EINVAL;
+    uint64_t total = 0;
+    uint32_t minl = UINT32_MAX, maxl = 0;
+    for (uint32_t j = 0; j < n_pats; j++) {
+        if (lens[j] == 0) return PFAC_EEMPTY_PATTERN;
+        if (!pats[j]) return PFAC_EINVAL;
+        if (lens[j] > kMaxPatternLen) return PFAC_ETOO_LARGE;
+        for (uint64_t i = 0; i < lens[j]; i++)
+            if (pats[j][i] >= alphabet) return PFAC_ESYMBOL;
+        total += lens[j];
+        minl = std::min<uint32_t>(minl, (uint32_t)lens[j]);
+        maxl = std::max<uint32_t>(maxl, (uint32_t)lens[j]);
+    }
+    if (n_pats == 0) minl = 0;
+    pfac_automaton *a = new (std::nothrow) pfac_automaton();
+    if (!a) return PFAC_ENOMEM;
+    try {
+        a->alphabet = alphabet;
+        a->n_pats = n_pats;
+        a->min_len = minl;
+        a->max_len = maxl;
+        a->nbw = (alphabet + 63) / 64;
+        std::vector<const uint8_t *> P(pats, pats + n_pats);
+        std::vector<uint32_t> L(n_pats);
+        for (uint32_t j = 0; j < n_pats; j++) L[j] = (uint32_t)lens[j];
+        // bytewise sort; a proper prefix sorts before its extensions; ties by id
+        std::vector<uint32_t> ord(n_pats);
+        for (uint32_t j = 0; j < n_pats; j++) ord[j] = j;
+        std::sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
+            uint32_t m = std::min(L[x], L[y]);
+            int c = memcmp(P[x], P[y], m);
+            if (c) return c < 0;
+            if (L[x] != L[y]) return L[x] < L[y];
+            return x < y;
+        });
+        // breadth-first construction, one level at a time
+        std::vector<Run> cur{{0, n_pats}}, nxt;
+        a->depth_start.push_back(0);
+        a->out_first.push_back(0);
+        uint32_t next_id = 1;  // index the next created node will get
+        for (uint32_t d = 0; !cur.empty(); d++) {
+            nxt.clear();
+            for (const Run &r : cur) {
+                uint32_t i = r.lo;
+                // patterns of length d end at this node (ids ascending: ties sorted by id)
+                while (i < r.hi && L[ord[i]] == d) a->out_ids.push_back(ord[i++]);
+                a->out_first.push_back((uint32_t)a->out_ids.size());
+                size_t base = a->bitmap.size();
+                a->bitmap.resize(base + a->nbw, 0);
+                a->first_child.push_back(i < r.hi ? next_id : 0);
+                while (i < r.hi) {
+                    uint8_t c = P[ord[i]][d];
+                    uint32_t j = i + 1;
+                    while (j < r.hi && P[ord[j]][d] == c) j++;
+                    nxt.push_back({i, j});
+                    a->bitmap[base + (c >> 6)] |= 1ull << (c & 63);
+                    if (next_id >= kMaxNodes) {
+                        delete a;
+                        return PFAC_ETOO_LARGE;
+                    }
+                    next_id++;
+                    i = j;
+                }
+            }
+            a->depth_start.push_back(a->depth_start.back() + (uint32_t)cur.size());
+            cur.swap(nxt);
+        }
+        a->n_nodes = (uint32_t)a->first_child.size();
+        while (a->depth_start.size() < (size_t)maxl + 3) a->depth_start.push_back(a->n_nodes);
+        a->n_term = 0;
+        for (uint32_t q = 0; q < a->n_nodes; q++)
+            if (a->out_first[q + 1] > a->out_first[q]) a->n_term++;
+
+        // device node images
+        if (alphabet <= 32) {
+            a->layout = LAYOUT_NARROW;
+            a->nw = 0;
+            a->dev_nodes.resize(a->n_nodes);
+            for (uint32_t q = 0; q < a->n_nodes; q++) {
+                uint64_t w = a->bitmap[(size_t)q * a->nbw] & 0xffffffffull;
+                w |= (uint64_t)a->first_child[q] << 32;
+                if (a->out_first[q + 1] > a->out_first[q]) w |= kTermBit;
+                a->dev_nodes[q] = w;
+            }
+        } else {
+            a->layout = LAYOUT_WIDE;
+            a->nw = a->nbw <= 1 ? 1 : a->nbw <= 2 ? 2 : 4;
+            a->dev_nodes.resize(a->n_nodes);
+            a->dev_bm.assign((size_t)a->n_nodes * a->nw, 0);
+            for (uint32_t q = 0; q < a->n_nodes; q++) {
+                const uint64_t *b = &a->bitmap[(size_t)q * a->nbw];
+                uint64_t r1 = 0, r2 = 0, r3 = 0;
+                for (uint32_t w = 0; w < a->nbw; w++) a->dev_bm[(size_t)q * a->nw + w] = b[w];
+                if (a->nbw > 1) r1 = popc64(b[0]);
+                if (a->nbw > 2) r2 = r1 + popc64(b[1]);
+                if (a->nbw > 3) r3 = r2 + popc64(b[2]);
+                uint64_t m = a->first_child[q] | (r1 << 32) | (r2 << 40) | (r3 << 48);
+                if (a->out_first[q + 1] > a->out_first[q]) m |= kTermBit;
+                a->dev_nodes[q] = m;
+            }
+        }
+        DevTable &t = a->shape;
+        t = DevTable{};
+        t.alphabet = alphabet;
+        t.layout = a->layout;
+        t.nw_log2 = a->nw == 4 ? 2 : a->nw == 2 ? 1 : 0;
+        t.n_nodes = a->n_nodes;
+        t.min_len = minl;
+        t.max_len = maxl;
+        build_lds_image(a, P);
+        (void)total;
+    } catch (const std::bad_alloc &) {
+        delete a;
+        return PFAC_ENOMEM;
+    }
+    *out = a;
+    return PFAC_OK;
+}
+
+}  // namespace pfac

@@ -1,0 +1,20 @@
+// Kernel launchers (device code lives in kernels_*.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pfac_impl.h"
+
+namespace pfac {
+
+// Plain scan (one lane per start, trie in HBM, count pass + emit pass).
+int launch_plain(const DevTable &t, const uint8_t *text, uint64_t n, uint64_t *keys,
+                 uint64_t cap, uint64_t *d_count, uint64_t *block_counts,
+                 uint64_t *block_offsets, hipStream_t s);
+uint64_t plain_blocks(uint64_t n);
+
+// Store one value to device memory (graph-capture safe: a kernel, not a memset).
+int launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t s);
+
+}  // namespace pfac

@@ -1,0 +1,107 @@
+// Internal definitions shared by the host builder, the HIP runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <vector>
+
+namespace pfac {
+
+// Node layouts in HBM.
+//
+// NARROW (alphabet <= 32): one 64-bit word per node:
+//     bits  0..31  child bitmap (bit c = symbol c)
+//     bits 32..62  first-child index (0 when the node has no child)
+//     bit  63      terminal: at least one pattern ends here
+//   This is the paper's 8-byte node at |Sigma| = 32 (Section 3.1) with the terminal flag
+//   taken from the top bit of the offset.
+//
+// WIDE (alphabet 33..256): bitmap words and per-node metadata in two arrays:
+//     bm[q * NW + w]  bits 64w .. 64w+63 of the child bitmap, NW = 1, 2 or 4
+//     meta[q]         bits  0..31 first-child index
+//                     bits 32..55 three rank bytes: set bits in words < 1, < 2, < 3
+//                     bit  63     terminal
+//   A lookup reads one bitmap word and the metadata word; Eq. 1's popcount then covers
+//   one 64-bit word plus a stored rank byte instead of up to four words.
+enum Layout : uint32_t { LAYOUT_NARROW = 0, LAYOUT_WIDE = 1 };
+
+constexpr uint64_t kTermBit = 1ull << 63;
+constexpr uint32_t kMaxPatternLen = 1u << 24;
+constexpr uint32_t kMaxNodes = 0x7fffffffu;
+
+// Per-workgroup LDS image (copied from HBM at kernel start), in 32-bit words:
+//   [root bitmap: 2^root_bits bits]      D-gram -> present?   (D = root_depth)
+//   [root rank: 2^(root_bits-5) u16]     set bits before each 32-bit word
+//   [filter: 2^filter_log2 bits]         hashed k-gram prefix filter (optional)
+// The root image folds the top D trie levels into one direct-indexed bitmap whose rank
+// (the popcount rule of Eq. 1 applied to a D-symbol root) is the breadth-first index of
+// the depth-D node: node = depth_start[D] + rank(key), keys in lexicographic order.
+struct DevTable {
+    const uint64_t *nodes;      // NARROW: node words. WIDE: meta words.
+    const uint64_t *bm;         // WIDE: bitmap words. NARROW: unused (null).
+    const uint32_t *out_first;  // n_nodes + 1: ids of q at out_ids[out_first[q] .. [q+1])
+    const uint32_t *out_ids;
+    const uint32_t *lds_image;  // see above
+    uint32_t alphabet;
+    uint32_t layout;            // Layout
+    uint32_t nw_log2;           // WIDE: log2(NW)
+    uint32_t n_nodes;
+    uint32_t min_len, max_len;
+    uint32_t pack2;             // 1: symbols coded in 2 bits (alphabet <= 4), else bytes
+    uint32_t root_depth;        // D (0 = no root image: walks start at node 0)
+    uint32_t root_bits;         // D * bits-per-symbol
+    uint32_t root_base;         // index of the first depth-D node
+    uint32_t filter_k;          // k (symbols per filter key); 0 = no hashed filter
+    uint32_t filter_log2;       // log2(filter bits)
+    uint32_t lds_words;         // total image size in 32-bit words
+    uint32_t rank_word;         // word offset of the rank table
+    uint32_t filter_word;       // word offset of the filter
+};
+
+constexpr uint32_t kFilterMul = 0x9E3779B1u;  // multiplicative hash (golden ratio)
+
+// Bit index of a k-gram key in a filter of 2^log2_bits bits (the builder and the
+// kernels must agree bit for bit).
+__host__ __device__ inline uint32_t filter_index(uint32_t key, uint32_t log2_bits) {
+    return (key * kFilterMul) >> (32 - log2_bits);
+}
+
+struct Workspace;  // per (device, stream) scratch, defined in the runtime
+
+struct DeviceCopy {
+    int device = -1;
+    void *nodes = nullptr, *bm = nullptr, *out_first = nullptr, *out_ids = nullptr,
+         *lds_image = nullptr;
+    DevTable view{};
+    std::map<void *, Workspace *> workspaces;  // keyed by stream
+};
+
+}  // namespace pfac
+
+struct pfac_automaton {
+    uint32_t alphabet = 0, n_pats = 0, n_nodes = 0, n_term = 0;
+    uint32_t min_len = 0, max_len = 0;
+    uint32_t layout = 0, nw = 0;  // nw: 64-bit bitmap words per node (WIDE)
+    // Paper layout (Section 3.1): first-child offset and the bitmap in 64-bit words.
+    std::vector<uint32_t> first_child;
+    std::vector<uint64_t> bitmap;      // n_nodes * nbw, nbw = ceil(alphabet / 64)
+    uint32_t nbw = 0;
+    std::vector<uint32_t> depth_start;  // first node of each depth, depth 0..max_len+1
+    std::vector<uint32_t> out_first, out_ids;
+    // Device images.
+    std::vector<uint64_t> dev_nodes, dev_bm;
+    std::vector<uint32_t> lds_image;
+    pfac::DevTable shape{};  // pointer fields null; filled per device copy
+    std::vector<pfac::DeviceCopy *> copies;
+    std::mutex mu;
+    ~pfac_automaton();
+};
+
+namespace pfac {
+int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
+                    uint32_t alphabet, pfac_automaton **out);
+void release_device_copies(pfac_automaton *a);
+}  // namespace pfac

@@ -1,0 +1,203 @@
+// Device side of the library: table upload, per-stream scratch, scan launches.
+#include <string.h>
+
+#include <new>
+
+#include "../../include/pfac.h"
+#include "kernels.h"
+#include "pfac_impl.h"
+
+namespace pfac {
+
+struct Workspace {
+    int device = -1;
+    uint64_t cap_blocks = 0;
+    uint64_t *block_counts = nullptr, *block_offsets = nullptr;
+    uint64_t *d_count = nullptr;  // count for the blocking scan
+    uint64_t *h_count = nullptr;  // pinned host mirror
+};
+
+namespace {
+
+__global__ void set_u64_kernel(uint64_t *dst, uint64_t v) { *dst = v; }
+
+int check_device(int device) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return PFAC_ENODEVICE;
+    if (device < 0 || device >= n) return PFAC_ENODEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PFAC_EHIP;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PFAC_ENODEVICE;
+    return PFAC_OK;
+}
+
+template <typename T>
+int upload_vec(const std::vector<T> &v, void **dst) {
+    size_t bytes = v.size() * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);  // keep a valid pointer for empty arrays
+    if (hipMalloc(dst, bytes) != hipSuccess) return PFAC_ENOMEM;
+    if (!v.empty() && hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return PFAC_EHIP;
+    return PFAC_OK;
+}
+
+void free_workspace(Workspace *w) {
+    if (!w) return;
+    hipFree(w->block_counts);
+    hipFree(w->block_offsets);
+    hipFree(w->d_count);
+    hipHostFree(w->h_count);
+    delete w;
+}
+
+void free_copy(DeviceCopy *c) {
+    if (!c) return;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(c->device);
+    for (auto &kv : c->workspaces) free_workspace(kv.second);
+    hipFree(c->nodes);
+    hipFree(c->bm);
+    hipFree(c->out_first);
+    hipFree(c->out_ids);
+    hipFree(c->lds_image);
+    hipSetDevice(prev);
+    delete c;
+}
+
+}  // namespace
+
+int launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t s) {
+    set_u64_kernel<<<1, 1, 0, s>>>(dst, value);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+void release_device_copies(pfac_automaton *a) {
+    for (DeviceCopy *c : a->copies) free_copy(c);
+    a->copies.clear();
+}
+
+// Device copy for the current device, uploading it on first use. Caller holds a->mu.
+static int get_copy(pfac_automaton *a, DeviceCopy **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PFAC_ENODEVICE;
+    for (DeviceCopy *c : a->copies)
+        if (c->device == dev) {
+            *out = c;
+            return PFAC_OK;
+        }
+    int rc = check_device(dev);
+    if (rc) return rc;
+    DeviceCopy *c = new (std::nothrow) DeviceCopy();
+    if (!c) return PFAC_ENOMEM;
+    c->device = dev;
+    rc = upload_vec(a->dev_nodes, &c->nodes);
+    if (!rc && a->layout == LAYOUT_WIDE) rc = upload_vec(a->dev_bm, &c->bm);
+    if (!rc) rc = upload_vec(a->out_first, &c->out_first);
+    if (!rc) rc = upload_vec(a->out_ids, &c->out_ids);
+    if (!rc) rc = upload_vec(a->lds_image, &c->lds_image);
+    if (rc) {
+        free_copy(c);
+        return rc;
+    }
+    c->view = a->shape;
+    c->view.nodes = (const uint64_t *)c->nodes;
+    c->view.bm = (const uint64_t *)c->bm;
+    c->view.out_first = (const uint32_t *)c->out_first;
+    c->view.out_ids = (const uint32_t *)c->out_ids;
+    c->view.lds_image = (const uint32_t *)c->lds_image;
+    a->copies.push_back(c);
+    *out = c;
+    return PFAC_OK;
+}
+
+static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, Workspace **out) {
+    Workspace *&w = c->workspaces[stream];
+    if (!w) {
+        w = new (std::nothrow) Workspace();
+        if (!w) return PFAC_ENOMEM;
+        w->device = c->device;
+        if (hipMalloc(&w->d_count, sizeof(uint64_t)) != hipSuccess) return PFAC_ENOMEM;
+        if (hipHostMalloc(&w->h_count, sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+            return PFAC_ENOMEM;
+    }
+    uint64_t nb = plain_blocks(n);
+    if (nb > w->cap_blocks) {
+        // the stream may still use the old buffers
+        if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
+        hipFree(w->block_counts);
+        hipFree(w->block_offsets);
+        w->block_counts = w->block_offsets = nullptr;
+        w->cap_blocks = 0;
+        uint64_t want = nb < 1024 ? 1024 : nb + nb / 4;
+        if (hipMalloc(&w->block_counts, want * 8) != hipSuccess) return PFAC_ENOMEM;
+        if (hipMalloc(&w->block_offsets, want * 8) != hipSuccess) return PFAC_ENOMEM;
+        w->cap_blocks = want;
+    }
+    *out = w;
+    return PFAC_OK;
+}
+
+}  // namespace pfac
+
+using namespace pfac;
+
+pfac_automaton::~pfac_automaton() { release_device_copies(this); }
+
+extern "C" int pfac_upload(pfac_automaton *a, int device) {
+    if (!a) return PFAC_EINVAL;
+    int rc = check_device(device);
+    if (rc) return rc;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return PFAC_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return PFAC_EHIP;
+    DeviceCopy *c = nullptr;
+    {
+        std::lock_guard<std::mutex> g(a->mu);
+        rc = get_copy(a, &c);
+    }
+    hipSetDevice(prev);
+    return rc;
+}
+
+static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
+                        uint64_t cap, uint64_t *d_count, void *stream, Workspace **ws_out) {
+    if (!a) return PFAC_EINVAL;
+    if (n > 0 && !d_text) return PFAC_EINVAL;
+    if (cap > 0 && !d_keys) return PFAC_EINVAL;
+    if (n >= (1ull << 32)) return PFAC_ETOO_LARGE;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> g(a->mu);
+    DeviceCopy *c = nullptr;
+    int rc = get_copy(a, &c);
+    if (rc) return rc;
+    Workspace *w = nullptr;
+    rc = get_workspace(c, stream, n, &w);
+    if (rc) return rc;
+    if (ws_out) *ws_out = w;
+    uint64_t *cnt = d_count ? d_count : w->d_count;
+    if (n == 0 || a->n_pats == 0) return launch_set_u64(cnt, 0, s) ? PFAC_EHIP : PFAC_OK;
+    if (launch_plain(c->view, d_text, n, d_keys, cap, cnt, w->block_counts, w->block_offsets, s))
+        return PFAC_EHIP;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t n,
+                               uint64_t *d_keys, uint64_t cap, uint64_t *d_count, void *stream) {
+    if (!d_count) return PFAC_EINVAL;
+    return scan_enqueue(a, d_text, n, d_keys, cap, d_count, stream, nullptr);
+}
+
+extern "C" int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
+                         uint64_t cap, uint64_t *h_count, void *stream) {
+    if (!h_count) return PFAC_EINVAL;
+    Workspace *w = nullptr;
+    int rc = scan_enqueue(a, d_text, n, d_keys, cap, nullptr, stream, &w);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(w->h_count, w->d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return PFAC_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return PFAC_EHIP;
+    *h_count = *w->h_count;
+    return *h_count > cap ? PFAC_ECAPACITY : PFAC_OK;
+}

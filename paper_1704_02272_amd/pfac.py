@@ -1,0 +1,214 @@
+"""Python binding of ``libpfac.so`` (argument marshalling only).
+
+Each function has the name of the C entry point it calls (``include/pfac.h``). Device
+buffers are torch tensors on a ROCm device; their ``data_ptr()`` and the current HIP
+stream are passed straight to the library, and every step of the matching runs in the
+library's HIP kernels. If the library is not built, or the device is not a gfx950,
+these functions raise: there is no fallback.
+
+Keys are returned in int64 tensors used as raw 64-bit storage: key = (start << 32) | id,
+which numpy reads back as uint64 (``keys.cpu().numpy().view(np.uint64)``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfac.so")
+
+PFAC_OK = 0
+PFAC_EINVAL = -1
+PFAC_EEMPTY_PATTERN = -2
+PFAC_ESYMBOL = -3
+PFAC_ETOO_LARGE = -4
+PFAC_ENOMEM = -5
+PFAC_EHIP = -6
+PFAC_ECAPACITY = -7
+PFAC_ENODEVICE = -8
+PFAC_EFORMAT = -9
+PFAC_ETIMEOUT = -10
+
+_lib = None
+
+
+class PfacError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (where, strerror(code) if _lib else "error", code))
+
+
+class TableInfo(C.Structure):
+    _fields_ = [(n, C.c_uint32) for n in (
+        "alphabet", "n_patterns", "n_nodes", "n_terminal_nodes", "min_len", "max_len",
+        "depth", "node_layout")] + [
+        ("paper_table_bytes", C.c_uint64), ("device_table_bytes", C.c_uint64)] + [
+        (n, C.c_uint32) for n in ("root_depth", "filter_k", "filter_log2_bits",
+                                  "lds_image_bytes")]
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpfac.so is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P8, P64, P32 = C.POINTER(C.c_uint8), C.POINTER(C.c_uint64), C.POINTER(C.c_uint32)
+        VP = C.c_void_p
+        sig = {
+            "pfac_strerror": (C.c_char_p, [C.c_int]),
+            "pfac_version": (C.c_int, []),
+            "pfac_build_csr": (C.c_int, [P8, P64, C.c_uint32, C.c_uint32, C.POINTER(VP)]),
+            "pfac_build": (C.c_int, [C.POINTER(P8), P64, C.c_uint32, C.c_uint32, C.POINTER(VP)]),
+            "pfac_destroy": (None, [VP]),
+            "pfac_table_info": (C.c_int, [VP, C.POINTER(TableInfo)]),
+            "pfac_export_paper_table": (C.c_int, [VP, P32, C.c_uint64, P32, C.c_uint64]),
+            "pfac_export_outputs": (C.c_int, [VP, P32, C.c_uint64, P32, C.c_uint64]),
+            "pfac_upload": (C.c_int, [VP, C.c_int]),
+            "pfac_scan_async": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
+            "pfac_scan": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, P64, VP]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().pfac_strerror(code).decode()
+
+
+def pfac_version() -> int:
+    return lib().pfac_version()
+
+
+def _check(rc: int, where: str):
+    if rc != PFAC_OK:
+        raise PfacError(rc, where)
+
+
+class Automaton:
+    """Owns a ``pfac_automaton*``; freed with ``pfac_destroy`` on close / collection."""
+
+    def __init__(self, handle: int, patterns_max_len: int):
+        self.handle = handle
+        self.max_len = patterns_max_len
+
+    def close(self):
+        if self.handle:
+            lib().pfac_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def pfac_build(patterns, alphabet: int = 256) -> Automaton:
+    """Build the compressed table of ``patterns`` (a list of bytes)."""
+    offs = np.zeros(len(patterns) + 1, dtype=np.uint64)
+    if patterns:
+        np.cumsum([len(p) for p in patterns], out=offs[1:])
+    data = np.frombuffer(b"".join(bytes(p) for p in patterns) or b"\0", dtype=np.uint8).copy()
+    h = C.c_void_p()
+    rc = lib().pfac_build_csr(data.ctypes.data_as(C.POINTER(C.c_uint8)),
+                              offs.ctypes.data_as(C.POINTER(C.c_uint64)), len(patterns),
+                              alphabet, C.byref(h))
+    _check(rc, "pfac_build")
+    return Automaton(h.value, max((len(p) for p in patterns), default=0))
+
+
+def pfac_table_info(a: Automaton) -> dict:
+    info = TableInfo()
+    _check(lib().pfac_table_info(a.handle, C.byref(info)), "pfac_table_info")
+    return {name: getattr(info, name) for name, _ in TableInfo._fields_}
+
+
+def pfac_export_paper_table(a: Automaton):
+    """(offsets uint32[n_nodes], bitmaps uint32[n_nodes, ceil(alphabet/32)])."""
+    info = pfac_table_info(a)
+    n, words = info["n_nodes"], (info["alphabet"] + 31) // 32
+    off = np.zeros(n, dtype=np.uint32)
+    bm = np.zeros((n, words), dtype=np.uint32)
+    P32 = C.POINTER(C.c_uint32)
+    _check(lib().pfac_export_paper_table(a.handle, off.ctypes.data_as(P32), n,
+                                         bm.ctypes.data_as(P32), bm.size),
+           "pfac_export_paper_table")
+    return off, bm
+
+
+def pfac_export_outputs(a: Automaton):
+    info = pfac_table_info(a)
+    first = np.zeros(info["n_nodes"] + 1, dtype=np.uint32)
+    ids = np.zeros(max(info["n_patterns"], 1), dtype=np.uint32)
+    P32 = C.POINTER(C.c_uint32)
+    _check(lib().pfac_export_outputs(a.handle, first.ctypes.data_as(P32), len(first),
+                                     ids.ctypes.data_as(P32), len(ids)), "pfac_export_outputs")
+    return first, ids[:info["n_patterns"]]
+
+
+def pfac_upload(a: Automaton, device: int = 0):
+    _check(lib().pfac_upload(a.handle, device), "pfac_upload")
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _device_u8(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.uint8 and t.is_contiguous()):
+        raise TypeError("text must be a contiguous uint8 tensor on a ROCm device")
+    return t
+
+
+def pfac_scan_async(a: Automaton, text, keys, count, stream=None):
+    """Enqueue a scan of ``text`` (uint8 device tensor). ``keys``: int64 device tensor
+    (capacity = its numel); ``count``: int64 device tensor with one element."""
+    text = _device_u8(text)
+    rc = lib().pfac_scan_async(a.handle, C.c_void_p(text.data_ptr()), text.numel(),
+                               C.c_void_p(keys.data_ptr() if keys.numel() else 0), keys.numel(),
+                               C.c_void_p(count.data_ptr()), _stream_handle(stream))
+    _check(rc, "pfac_scan_async")
+
+
+def pfac_scan(a: Automaton, text, keys=None, stream=None):
+    """Blocking scan. Returns the keys of all matches as an int64 device tensor (raw
+    uint64 keys, sorted). If ``keys`` is given it is used as the output buffer first;
+    on PFAC_ECAPACITY a buffer of the needed size is allocated and the scan repeated."""
+    import torch
+    text = _device_u8(text)
+    if keys is None:
+        keys = torch.empty(max(1024, text.numel() // 256), dtype=torch.int64, device=text.device)
+    cnt = C.c_uint64(0)
+    for _ in range(2):
+        rc = lib().pfac_scan(a.handle, C.c_void_p(text.data_ptr()), text.numel(),
+                             C.c_void_p(keys.data_ptr()), keys.numel(), C.byref(cnt),
+                             _stream_handle(stream))
+        if rc == PFAC_ECAPACITY:
+            keys = torch.empty(int(cnt.value), dtype=torch.int64, device=text.device)
+            continue
+        _check(rc, "pfac_scan")
+        return keys[:int(cnt.value)]
+    raise PfacError(PFAC_ECAPACITY, "pfac_scan")
+
+
+def keys_to_numpy(keys) -> np.ndarray:
+    """Device int64 key tensor -> host uint64 array."""
+    return keys.cpu().numpy().view(np.uint64)

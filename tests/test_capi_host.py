@@ -1,0 +1,115 @@
+"""The C ABI on the host (no GPU): the library loads and exports every symbol the header
+declares; building validates its input; the table it builds is, bit for bit, the
+Section 3.1 layout the oracle writes out from its definition."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1704_02272_amd.pfac as pfac
+from oracle import trie
+from paper_1704_02272_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfac.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"PFAC_API\s+[\w\s\*]*?\b(pfac_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 10
+    L = C.CDLL(pfac.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings_and_version():
+    assert pfac.strerror(pfac.PFAC_OK) == "ok"
+    for code in range(-10, 0):
+        assert pfac.strerror(code) != "unknown status"
+    assert pfac.pfac_version() >= 10000
+
+
+@pytest.mark.parametrize("pats,alphabet,code", [
+    ([b"ab", b""], 256, pfac.PFAC_EEMPTY_PATTERN),
+    ([b"ab", b"\x04"], 4, pfac.PFAC_ESYMBOL),
+    ([b"ab"], 0, pfac.PFAC_EINVAL),
+    ([b"ab"], 257, pfac.PFAC_EINVAL),
+])
+def test_build_errors(pats, alphabet, code):
+    with pytest.raises(pfac.PfacError) as e:
+        pfac.pfac_build(pats, alphabet)
+    assert e.value.code == code
+
+
+def test_build_null_arguments():
+    L = pfac.lib()
+    h = C.c_void_p()
+    assert L.pfac_build_csr(None, None, 3, 256, C.byref(h)) == pfac.PFAC_EINVAL
+    assert L.pfac_build_csr(None, None, 0, 256, None) == pfac.PFAC_EINVAL
+    assert L.pfac_table_info(None, None) == pfac.PFAC_EINVAL
+
+
+def _paper_arrays(pats, alphabet):
+    off, bms = trie.paper_layout(pats, alphabet)
+    words = (alphabet + 31) // 32
+    bm = np.array([[(b >> (32 * w)) & 0xFFFFFFFF for w in range(words)] for b in bms],
+                  dtype=np.uint32).reshape(len(bms), words)
+    return np.array(off, dtype=np.uint32), bm
+
+
+def _check_table(pats, alphabet):
+    a = pfac.pfac_build(pats, alphabet)
+    off, bm = pfac.pfac_export_paper_table(a)
+    want_off, want_bm = _paper_arrays(pats, alphabet)
+    assert np.array_equal(off, want_off)
+    assert np.array_equal(bm, want_bm)
+    info = pfac.pfac_table_info(a)
+    assert info["n_nodes"] == len(want_off)
+    assert info["paper_table_bytes"] == trie.paper_table_bytes(len(want_off), alphabet)
+    # pattern ids per node: the ids of the patterns that spell that node's string
+    first, ids = pfac.pfac_export_outputs(a)
+    nodes = trie.canonical_nodes(pats)
+    for q, s in enumerate(nodes):
+        want = [j for j, p in enumerate(pats) if p == s]
+        assert list(ids[first[q]:first[q + 1]]) == want
+    return a, info
+
+
+def test_worked_example_table():
+    a, info = _check_table([b"AB", b"AD", b"Z"], 256)
+    off, bm = pfac.pfac_export_paper_table(a)
+    assert off[1] == 3 and (bm[1][2] >> (66 - 64)) & 1 and (bm[1][2] >> (68 - 64)) & 1
+    assert info["n_nodes"] == 5
+
+
+def test_random_tables_match_layout_model():
+    rng = np.random.default_rng(21)
+    for trial in range(60):
+        sigma = int(rng.choice([1, 2, 4, 5, 26, 32, 33, 64, 65, 128, 200, 256]))
+        pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(1, 10))).astype(np.uint8))
+                for _ in range(int(rng.integers(1, 60)))]
+        _check_table(pats, sigma)
+
+
+def test_workload_tables_match_layout_model():
+    _check_table(W.uniform_256().patterns, 256)
+    _check_table(W.dna_4(text_bytes=1 << 12, n_patterns=2000).patterns, 4)
+    _check_table(W.printable_256(text_bytes=1 << 16, n_patterns=1500).patterns, 256)
+
+
+def test_node_layout_choice():
+    assert pfac.pfac_table_info(pfac.pfac_build([b"\x01\x02"], 32))["node_layout"] == 0
+    assert pfac.pfac_table_info(pfac.pfac_build([b"\x01\x02"], 33))["node_layout"] == 1
+
+
+def test_empty_pattern_set():
+    a = pfac.pfac_build([], 256)
+    info = pfac.pfac_table_info(a)
+    assert info["n_nodes"] == 1 and info["n_patterns"] == 0

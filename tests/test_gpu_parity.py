@@ -1,0 +1,142 @@
+"""GPU parity: keys from the HIP path, through the C ABI, equal the oracle's element by
+element (bit-exact: this is integer work).
+
+Covers the hand cases, random small cases over many alphabets (several tiles and a
+ragged tail), the capacity-overflow protocol, and the full-size workloads: 1 MiB
+uniform (alphabet 256, 100 patterns), 256 MiB printable (5,000 patterns) and 1 GiB
+DNA (alphabet 4, 10,000 patterns)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1704_02272_amd.pfac as pfac  # noqa: E402
+from oracle import literal, native  # noqa: E402
+from paper_1704_02272_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DEV = "cuda:0"
+
+
+def _keys(pairs):
+    return np.array([(s << 32) | j for s, j in pairs], dtype=np.uint64)
+
+
+def gpu_scan(a, text_np, **kw):
+    t = torch.from_numpy(np.array(text_np, dtype=np.uint8, copy=True)).to(DEV)
+    k = pfac.pfac_scan(a, t, **kw)
+    torch.cuda.synchronize()
+    return pfac.keys_to_numpy(k)
+
+
+def _hand():
+    with open(os.path.join(GOLDEN, "hand_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _hand(), ids=lambda c: c["name"])
+def test_hand_cases(case):
+    pats = [bytes.fromhex(p) for p in case["patterns"]]
+    text = np.frombuffer(bytes.fromhex(case["text"]), dtype=np.uint8)
+    a = pfac.pfac_build(pats, case["alphabet"])
+    got = gpu_scan(a, text)
+    assert np.array_equal(got, _keys([tuple(x) for x in case["expected"]]))
+
+
+def test_random_small_cases():
+    rng = np.random.default_rng(1234)
+    for trial in range(120):
+        sigma = int(rng.choice([1, 2, 3, 4, 5, 16, 32, 33, 64, 100, 256]))
+        npat = int(rng.integers(1, 80))
+        maxl = int(rng.choice([3, 8, 20, 70]))
+        pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(1, maxl + 1))).astype(np.uint8))
+                for _ in range(npat)]
+        n = int(rng.choice([0, 1, 7, 100, 4095, 4096, 4097, 70000, 300001]))
+        hi = min(256, sigma + (2 if trial % 4 == 0 else 0))
+        text = rng.integers(0, hi, size=n).astype(np.uint8)
+        # plant a few patterns so matches exist at any alphabet
+        for _ in range(min(20, n // 8)):
+            p = pats[int(rng.integers(0, npat))]
+            if len(p) <= n:
+                o = int(rng.integers(0, n - len(p) + 1))
+                text[o:o + len(p)] = np.frombuffer(p, dtype=np.uint8)
+        a = pfac.pfac_build(pats, sigma)
+        want = native.AhoCorasick(pats, sigma).scan(text, chunk=1 << 16)
+        got = gpu_scan(a, text)
+        assert np.array_equal(got, want), (trial, sigma, npat, n)
+
+
+def test_long_patterns_past_any_halo():
+    rng = np.random.default_rng(5)
+    base = rng.integers(0, 256, size=5000).astype(np.uint8).tobytes()
+    pats = [base[:3000], base[:10], base[100:2100], b"\x00\x01"]
+    text = np.frombuffer(base * 3, dtype=np.uint8).copy()
+    a = pfac.pfac_build(pats, 256)
+    assert np.array_equal(gpu_scan(a, text), native.AhoCorasick(pats, 256).scan(text))
+
+
+def test_capacity_overflow_protocol():
+    pats = [b"a", b"aa"]
+    text = np.frombuffer(b"a" * 5000, dtype=np.uint8)
+    a = pfac.pfac_build(pats, 256)
+    t = torch.from_numpy(text.copy()).to(DEV)
+    small = torch.empty(10, dtype=torch.int64, device=DEV)
+    got = pfac.keys_to_numpy(pfac.pfac_scan(a, t, keys=small))
+    assert len(got) == 5000 + 4999
+    assert np.array_equal(got, literal.keys(literal.match_set(pats, text.tobytes())))
+
+
+def test_async_count_and_no_patterns():
+    a = pfac.pfac_build([b"xyz"], 256)
+    t = torch.from_numpy(np.frombuffer(b"..xyz..xyz", dtype=np.uint8).copy()).to(DEV)
+    keys = torch.empty(16, dtype=torch.int64, device=DEV)
+    cnt = torch.full((1,), -1, dtype=torch.int64, device=DEV)
+    pfac.pfac_scan_async(a, t, keys, cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 2
+    assert list(pfac.keys_to_numpy(keys[:2])) == [(2 << 32), (7 << 32)]
+    e = pfac.pfac_build([], 256)
+    pfac.pfac_scan_async(e, t, keys, cnt)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 0
+
+
+def test_uniform_1mib_full():
+    w = W.uniform_256()
+    a = pfac.pfac_build(w.patterns, 256)
+    got = gpu_scan(a, w.text)
+    assert np.array_equal(got, native.brute(w.patterns, w.text))
+
+
+@pytest.mark.timeout(600)
+def test_printable_256mib_full_and_repeatable():
+    w = W.printable_256()
+    a = pfac.pfac_build(w.patterns, 256)
+    want = native.AhoCorasick(w.patterns, 256).scan(w.text)
+    t = torch.from_numpy(w.text).to(DEV)
+    got1 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    got2 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    assert np.array_equal(got1, want)
+    assert np.array_equal(got2, want)
+    # brute force on sampled windows (the definition, independent of the automaton)
+    rng = np.random.default_rng(0)
+    for _ in range(8):
+        o = int(rng.integers(0, len(w.text) - (1 << 16)))
+        win = w.text[o:o + (1 << 16) + w.max_len - 1]
+        b = native.brute(w.patterns, win)
+        b = b[(b >> np.uint64(32)) < (1 << 16)] + np.uint64(o << 32)
+        lo, hi = np.uint64(o << 32), np.uint64((o + (1 << 16)) << 32)
+        assert np.array_equal(got1[(got1 >= lo) & (got1 < hi)], b)
+
+
+@pytest.mark.timeout(900)
+def test_dna_1gib_full():
+    w = W.dna_4()
+    a = pfac.pfac_build(w.patterns, 4)
+    want = native.AhoCorasick(w.patterns, 4).scan(w.text)
+    got = gpu_scan(a, w.text, keys=torch.empty(len(want) + 16, dtype=torch.int64, device=DEV))
+    assert np.array_equal(got, want)
