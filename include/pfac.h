@@ -145,6 +145,26 @@ PFAC_API int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t 
 PFAC_API int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
                        uint64_t cap, uint64_t *h_count, void *stream);
 
+/* ------------------------------------------------------------------- tuning
+ * Launch choices of an automaton's scans. None of them changes any result.
+ *   algo  PFAC_ALGO_AUTO (= TILED), PFAC_ALGO_PLAIN (one lane per start, trie walked
+ *         from the root in HBM, count pass + emit pass: the design of Section 2.3 as
+ *         printed, kept as a baseline), PFAC_ALGO_TILED (persistent tiled kernel with
+ *         the LDS prefilter and root image).
+ *   grid  workgroups of the persistent tiled kernel (0 = as many as fit on the device).
+ * Errors: PFAC_EINVAL. */
+#define PFAC_ALGO_AUTO 0u
+#define PFAC_ALGO_PLAIN 1u
+#define PFAC_ALGO_TILED 2u
+typedef struct {
+    uint32_t algo;
+    uint32_t grid;
+    uint32_t reserved[6];
+} pfac_tuning;
+
+PFAC_API int pfac_set_tuning(pfac_automaton *a, const pfac_tuning *t);
+PFAC_API int pfac_get_tuning(const pfac_automaton *a, pfac_tuning *t);
+
 #ifdef __cplusplus
 }
 #endif

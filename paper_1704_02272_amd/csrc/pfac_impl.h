@@ -85,6 +85,7 @@ struct pfac_automaton {
     uint32_t alphabet = 0, n_pats = 0, n_nodes = 0, n_term = 0;
     uint32_t min_len = 0, max_len = 0;
     uint32_t layout = 0, nw = 0;  // nw: 64-bit bitmap words per node (WIDE)
+    uint32_t algo = 0, grid = 0;  // tuning: kernel choice, persistent grid (0 = auto)
     // Paper layout (Section 3.1): first-child offset and the bitmap in 64-bit words.
     std::vector<uint32_t> first_child;
     std::vector<uint64_t> bitmap;      // n_nodes * nbw, nbw = ceil(alphabet / 64)

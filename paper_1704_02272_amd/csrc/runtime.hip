@@ -1,18 +1,23 @@
 // Device side of the library: table upload, per-stream scratch, scan launches.
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "../../include/pfac.h"
 #include "kernels.h"
 #include "pfac_impl.h"
+#include "scan_internal.h"
 
 namespace pfac {
 
 struct Workspace {
     int device = -1;
-    uint64_t cap_blocks = 0;
+    uint64_t cap_blocks = 0;  // plain scan: per-block counts and offsets
     uint64_t *block_counts = nullptr, *block_offsets = nullptr;
+    uint64_t cap_tiles = 0;   // tiled scan: look-back state
+    TileState ts{};
+    uint64_t launches = 0;    // tiled launches since the tile words were last cleared
     uint64_t *d_count = nullptr;  // count for the blocking scan
     uint64_t *h_count = nullptr;  // pinned host mirror
 };
@@ -41,8 +46,27 @@ int upload_vec(const std::vector<T> &v, void **dst) {
     return PFAC_OK;
 }
 
+void free_tiles(Workspace *w) {
+    hipFree(w->ts.word);
+    hipFree(w->ts.ctrl);
+    w->ts = TileState{};
+    w->cap_tiles = 0;
+}
+
+__global__ void clear_tiles_kernel(uint64_t *word, uint64_t n, uint32_t *ctrl) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        word[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctrl[0] = 0;
+        ctrl[1] = 0;
+        ctrl[2] = 1;
+        ctrl[3] = 0;
+    }
+}
+
 void free_workspace(Workspace *w) {
     if (!w) return;
+    free_tiles(w);
     hipFree(w->block_counts);
     hipFree(w->block_offsets);
     hipFree(w->d_count);
@@ -111,7 +135,7 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     return PFAC_OK;
 }
 
-static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, Workspace **out) {
+static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo, Workspace **out) {
     Workspace *&w = c->workspaces[stream];
     if (!w) {
         w = new (std::nothrow) Workspace();
@@ -120,6 +144,27 @@ static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, Workspace **ou
         if (hipMalloc(&w->d_count, sizeof(uint64_t)) != hipSuccess) return PFAC_ENOMEM;
         if (hipHostMalloc(&w->h_count, sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
             return PFAC_ENOMEM;
+    }
+    if (algo == PFAC_ALGO_TILED) {
+        uint64_t nt = (n + kTile - 1) / kTile;
+        if (nt > w->cap_tiles || !w->ts.ctrl) {
+            if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
+            free_tiles(w);
+            uint64_t want = nt < 4096 ? 4096 : nt + nt / 4;
+            if (hipMalloc(&w->ts.word, want * 8) != hipSuccess) return PFAC_ENOMEM;
+            if (hipMalloc(&w->ts.ctrl, 16) != hipSuccess) return PFAC_ENOMEM;
+            w->cap_tiles = want;
+            w->launches = kEpochPeriod;  // forces a clear before the first launch
+        }
+        if (w->launches >= kEpochPeriod) {
+            // words 0 never match an epoch (epochs start at 1); clearing before the
+            // device epoch can wrap keeps stale words from ever matching
+            clear_tiles_kernel<<<256, 256, 0, (hipStream_t)stream>>>(w->ts.word, w->cap_tiles, w->ts.ctrl);
+            if (hipGetLastError() != hipSuccess) return PFAC_EHIP;
+            w->launches = 0;
+        }
+        *out = w;
+        return PFAC_OK;
     }
     uint64_t nb = plain_blocks(n);
     if (nb > w->cap_blocks) {
@@ -171,14 +216,23 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, ui
     DeviceCopy *c = nullptr;
     int rc = get_copy(a, &c);
     if (rc) return rc;
+    const uint32_t algo = a->algo == PFAC_ALGO_PLAIN ? PFAC_ALGO_PLAIN : PFAC_ALGO_TILED;
     Workspace *w = nullptr;
-    rc = get_workspace(c, stream, n, &w);
+    rc = get_workspace(c, stream, n, algo, &w);
     if (rc) return rc;
     if (ws_out) *ws_out = w;
     uint64_t *cnt = d_count ? d_count : w->d_count;
     if (n == 0 || a->n_pats == 0) return launch_set_u64(cnt, 0, s) ? PFAC_EHIP : PFAC_OK;
-    if (launch_plain(c->view, d_text, n, d_keys, cap, cnt, w->block_counts, w->block_offsets, s))
+    if (algo == PFAC_ALGO_PLAIN) {
+        if (launch_plain(c->view, d_text, n, d_keys, cap, cnt, w->block_counts, w->block_offsets, s))
+            return PFAC_EHIP;
+        return PFAC_OK;
+    }
+    const uint64_t nt = (n + kTile - 1) / kTile;
+    const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, nt) : scan_grid(c->view, nt);
+    if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, cnt, w->ts, grid, s))
         return PFAC_EHIP;
+    w->launches++;
     return PFAC_OK;
 }
 
@@ -199,5 +253,24 @@ extern "C" int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, u
         return PFAC_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return PFAC_EHIP;
     *h_count = *w->h_count;
+    if (*h_count == kCountTimeout) return PFAC_ETIMEOUT;
+    if (*h_count == kCountOverflow) return PFAC_ETOO_LARGE;
     return *h_count > cap ? PFAC_ECAPACITY : PFAC_OK;
+}
+
+extern "C" int pfac_set_tuning(pfac_automaton *a, const pfac_tuning *t) {
+    if (!a || !t) return PFAC_EINVAL;
+    if (t->algo > PFAC_ALGO_TILED) return PFAC_EINVAL;
+    std::lock_guard<std::mutex> g(a->mu);
+    a->algo = t->algo;
+    a->grid = t->grid;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_get_tuning(const pfac_automaton *a, pfac_tuning *t) {
+    if (!a || !t) return PFAC_EINVAL;
+    memset(t, 0, sizeof(*t));
+    t->algo = a->algo == PFAC_ALGO_PLAIN ? PFAC_ALGO_PLAIN : PFAC_ALGO_TILED;
+    t->grid = a->grid;
+    return PFAC_OK;
 }

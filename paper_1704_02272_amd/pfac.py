@@ -49,6 +49,14 @@ class TableInfo(C.Structure):
                                   "lds_image_bytes")]
 
 
+PFAC_ALGO_AUTO, PFAC_ALGO_PLAIN, PFAC_ALGO_TILED = 0, 1, 2
+ALGOS = {"auto": PFAC_ALGO_AUTO, "plain": PFAC_ALGO_PLAIN, "tiled": PFAC_ALGO_TILED}
+
+
+class Tuning(C.Structure):
+    _fields_ = [("algo", C.c_uint32), ("grid", C.c_uint32), ("reserved", C.c_uint32 * 6)]
+
+
 def lib():
     """The loaded library (raises if it has not been built)."""
     global _lib
@@ -70,6 +78,8 @@ def lib():
             "pfac_upload": (C.c_int, [VP, C.c_int]),
             "pfac_scan_async": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
             "pfac_scan": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, P64, VP]),
+            "pfac_set_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
+            "pfac_get_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -158,6 +168,18 @@ def pfac_export_outputs(a: Automaton):
     _check(lib().pfac_export_outputs(a.handle, first.ctypes.data_as(P32), len(first),
                                      ids.ctypes.data_as(P32), len(ids)), "pfac_export_outputs")
     return first, ids[:info["n_patterns"]]
+
+
+def pfac_set_tuning(a: Automaton, algo: str = "auto", grid: int = 0):
+    t = Tuning(ALGOS[algo], grid)
+    _check(lib().pfac_set_tuning(a.handle, C.byref(t)), "pfac_set_tuning")
+
+
+def pfac_get_tuning(a: Automaton) -> dict:
+    t = Tuning()
+    _check(lib().pfac_get_tuning(a.handle, C.byref(t)), "pfac_get_tuning")
+    name = {v: k for k, v in ALGOS.items()}[t.algo]
+    return {"algo": name, "grid": t.grid}
 
 
 def pfac_upload(a: Automaton, device: int = 0):

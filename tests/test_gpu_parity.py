@@ -26,6 +26,15 @@ def _keys(pairs):
     return np.array([(s << 32) | j for s, j in pairs], dtype=np.uint64)
 
 
+ALGOS = ["tiled", "plain"]
+
+
+def build(pats, alphabet, algo="tiled", grid=0):
+    a = pfac.pfac_build(pats, alphabet)
+    pfac.pfac_set_tuning(a, algo=algo, grid=grid)
+    return a
+
+
 def gpu_scan(a, text_np, **kw):
     t = torch.from_numpy(np.array(text_np, dtype=np.uint8, copy=True)).to(DEV)
     k = pfac.pfac_scan(a, t, **kw)
@@ -38,16 +47,18 @@ def _hand():
         return json.load(f)["cases"]
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("case", _hand(), ids=lambda c: c["name"])
-def test_hand_cases(case):
+def test_hand_cases(case, algo):
     pats = [bytes.fromhex(p) for p in case["patterns"]]
     text = np.frombuffer(bytes.fromhex(case["text"]), dtype=np.uint8)
-    a = pfac.pfac_build(pats, case["alphabet"])
+    a = build(pats, case["alphabet"], algo)
     got = gpu_scan(a, text)
     assert np.array_equal(got, _keys([tuple(x) for x in case["expected"]]))
 
 
-def test_random_small_cases():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_random_small_cases(algo):
     rng = np.random.default_rng(1234)
     for trial in range(120):
         sigma = int(rng.choice([1, 2, 3, 4, 5, 16, 32, 33, 64, 100, 256]))
@@ -64,29 +75,31 @@ def test_random_small_cases():
             if len(p) <= n:
                 o = int(rng.integers(0, n - len(p) + 1))
                 text[o:o + len(p)] = np.frombuffer(p, dtype=np.uint8)
-        a = pfac.pfac_build(pats, sigma)
+        a = build(pats, sigma, algo, grid=int(rng.choice([0, 1, 3])))
         want = native.AhoCorasick(pats, sigma).scan(text, chunk=1 << 16)
         got = gpu_scan(a, text)
         assert np.array_equal(got, want), (trial, sigma, npat, n)
 
 
-def test_long_patterns_past_any_halo():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_long_patterns_past_any_halo(algo):
     rng = np.random.default_rng(5)
     base = rng.integers(0, 256, size=5000).astype(np.uint8).tobytes()
     pats = [base[:3000], base[:10], base[100:2100], b"\x00\x01"]
     text = np.frombuffer(base * 3, dtype=np.uint8).copy()
-    a = pfac.pfac_build(pats, 256)
+    a = build(pats, 256, algo)
     assert np.array_equal(gpu_scan(a, text), native.AhoCorasick(pats, 256).scan(text))
 
 
-def test_capacity_overflow_protocol():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_capacity_overflow_protocol(algo):
     pats = [b"a", b"aa"]
-    text = np.frombuffer(b"a" * 5000, dtype=np.uint8)
-    a = pfac.pfac_build(pats, 256)
+    text = np.frombuffer(b"a" * 50000, dtype=np.uint8)
+    a = build(pats, 256, algo)
     t = torch.from_numpy(text.copy()).to(DEV)
     small = torch.empty(10, dtype=torch.int64, device=DEV)
     got = pfac.keys_to_numpy(pfac.pfac_scan(a, t, keys=small))
-    assert len(got) == 5000 + 4999
+    assert len(got) == 50000 + 49999
     assert np.array_equal(got, literal.keys(literal.match_set(pats, text.tobytes())))
 
 
@@ -105,9 +118,10 @@ def test_async_count_and_no_patterns():
     assert int(cnt.item()) == 0
 
 
-def test_uniform_1mib_full():
+@pytest.mark.parametrize("algo", ALGOS)
+def test_uniform_1mib_full(algo):
     w = W.uniform_256()
-    a = pfac.pfac_build(w.patterns, 256)
+    a = build(w.patterns, 256, algo)
     got = gpu_scan(a, w.text)
     assert np.array_equal(got, native.brute(w.patterns, w.text))
 
@@ -115,11 +129,14 @@ def test_uniform_1mib_full():
 @pytest.mark.timeout(600)
 def test_printable_256mib_full_and_repeatable():
     w = W.printable_256()
-    a = pfac.pfac_build(w.patterns, 256)
+    a = build(w.patterns, 256, "tiled")
     want = native.AhoCorasick(w.patterns, 256).scan(w.text)
     t = torch.from_numpy(w.text).to(DEV)
     got1 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
     got2 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    pfac.pfac_set_tuning(a, algo="plain")
+    got3 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    assert np.array_equal(got3, want)
     assert np.array_equal(got1, want)
     assert np.array_equal(got2, want)
     # brute force on sampled windows (the definition, independent of the automaton)
@@ -136,7 +153,20 @@ def test_printable_256mib_full_and_repeatable():
 @pytest.mark.timeout(900)
 def test_dna_1gib_full():
     w = W.dna_4()
-    a = pfac.pfac_build(w.patterns, 4)
+    a = build(w.patterns, 4, "tiled")
     want = native.AhoCorasick(w.patterns, 4).scan(w.text)
     got = gpu_scan(a, w.text, keys=torch.empty(len(want) + 16, dtype=torch.int64, device=DEV))
     assert np.array_equal(got, want)
+
+
+def test_grid_sizes_and_repeats_agree():
+    """Metamorphic: the persistent grid size (1, 2, 7, auto) and repeated launches on a
+    reused workspace leave the keys unchanged (look-back, ticket and epoch reuse)."""
+    w = W.printable_256(text_bytes=6 << 20, n_patterns=3000, plant_block=1 << 12)
+    want = native.AhoCorasick(w.patterns, 256).scan(w.text)
+    t = torch.from_numpy(w.text).to(DEV)
+    for grid in (1, 2, 7, 0, 0):
+        a = build(w.patterns, 256, "tiled", grid)
+        for _ in range(2):
+            assert np.array_equal(pfac.keys_to_numpy(pfac.pfac_scan(a, t)), want), grid
+        torch.cuda.synchronize()
