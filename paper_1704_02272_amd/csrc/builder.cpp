@@ -12,7 +12,7 @@
 #include <algorithm>
 #include <new>
 
-#include "../../include/pfac.h"
+#include "pfac.h"
 #include "pfac_impl.h"
 
 namespace pfac {
@@ -74,10 +74,10 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
         for (uint32_t j = 0; j < a->n_pats; j++) fkeys.push_back(filter_key(P[j], K, t.pack2));
         std::sort(fkeys.begin(), fkeys.end());
         fkeys.erase(std::unique(fkeys.begin(), fkeys.end()), fkeys.end());
-        // about 64 filter bits per distinct prefix, between 8 Kibit and 256 Kibit
-        uint64_t want = (uint64_t)fkeys.size() * 64;
+        // about 32 filter bits per distinct prefix, between 8 and 128 Kibit (1-16 KiB)
+        uint64_t want = (uint64_t)fkeys.size() * 32;
         flog2 = 13;
-        while (flog2 < 18 && (1ull << flog2) < want) flog2++;
+        while (flog2 < 17 && (1ull << flog2) < want) flog2++;
     }
     t.filter_k = K > D ? K : 0;
     t.filter_log2 = flog2;
@@ -100,10 +100,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
     // every depth-D node is a D-prefix of some pattern (D <= shortest length)
     if (run != a->depth_start[D + 1] - a->depth_start[D]) throw std::bad_alloc();
     uint32_t *filt = img + t.filter_word;
-    for (uint32_t key : fkeys) {
-        uint32_t b = filter_index(key, flog2);
-        filt[b >> 5] |= 1u << (b & 31);
-    }
+    for (uint32_t key : fkeys) bloom_insert(filt, key, flog2);
 }
 
 }  // namespace

@@ -3,7 +3,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/pfac.h"
+#include "pfac.h"
 #include "pfac_impl.h"
 
 using namespace pfac;

@@ -35,7 +35,7 @@ constexpr uint32_t kMaxNodes = 0x7fffffffu;
 // Per-workgroup LDS image (copied from HBM at kernel start), in 32-bit words:
 //   [root bitmap: 2^root_bits bits]      D-gram -> present?   (D = root_depth)
 //   [root rank: 2^(root_bits-5) u16]     set bits before each 32-bit word
-//   [filter: 2^filter_log2 bits]         hashed k-gram prefix filter (optional)
+//   [filter: 2^filter_log2 bits]         blocked Bloom filter of k-gram prefixes (optional)
 // The root image folds the top D trie levels into one direct-indexed bitmap whose rank
 // (the popcount rule of Eq. 1 applied to a D-symbol root) is the breadth-first index of
 // the depth-D node: node = depth_start[D] + rank(key), keys in lexicographic order.
@@ -63,10 +63,13 @@ struct DevTable {
 
 constexpr uint32_t kFilterMul = 0x9E3779B1u;  // multiplicative hash (golden ratio)
 
-// Bit index of a k-gram key in a filter of 2^log2_bits bits (the builder and the
-// kernels must agree bit for bit).
-__host__ __device__ inline uint32_t filter_index(uint32_t key, uint32_t log2_bits) {
-    return (key * kFilterMul) >> (32 - log2_bits);
+// Blocked Bloom filter over k-gram keys, 2^log2_bits bits (log2_bits in 13..21): a key
+// sets two bits of one 32-bit word. h = key * kFilterMul; word = the top log2_bits - 5
+// bits of h; bits (h >> 6) & 31 and (h >> 11) & 31. The builder and the kernels must
+// agree bit for bit.
+inline void bloom_insert(uint32_t *F, uint32_t key, uint32_t log2_bits) {
+    const uint32_t h = key * kFilterMul;
+    F[h >> (37 - log2_bits)] |= (1u << ((h >> 6) & 31)) | (1u << ((h >> 11) & 31));
 }
 
 struct Workspace;  // per (device, stream) scratch, defined in the runtime

@@ -4,7 +4,7 @@
 #include <algorithm>
 #include <new>
 
-#include "../../include/pfac.h"
+#include "pfac.h"
 #include "kernels.h"
 #include "pfac_impl.h"
 #include "scan_internal.h"
@@ -146,7 +146,7 @@ static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo,
             return PFAC_ENOMEM;
     }
     if (algo == PFAC_ALGO_TILED) {
-        uint64_t nt = (n + kTile - 1) / kTile;
+        uint64_t nt = (n + kSpan - 1) / kSpan;
         if (nt > w->cap_tiles || !w->ts.ctrl) {
             if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
             free_tiles(w);
@@ -228,8 +228,8 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, ui
             return PFAC_EHIP;
         return PFAC_OK;
     }
-    const uint64_t nt = (n + kTile - 1) / kTile;
-    const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, nt) : scan_grid(c->view, nt);
+    const uint64_t nt = (n + kSpan - 1) / kSpan;
+    const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, nt) : 0u;
     if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, cnt, w->ts, grid, s))
         return PFAC_EHIP;
     w->launches++;
