@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mode", default="scan", choices=["scan", "copy"],
+                    help="copy: a plain device-to-device copy of the workload's text, the "
+                         "reference that scales the HBM byte counters of the scan")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -122,6 +125,13 @@ def main():
     if args.algo != "auto":
         pfac.pfac_set_tuning(a, algo=args.algo)
     texts = [torch.from_numpy(w.text).to(dev) for _ in range(max(1, args.copies))]
+    if args.mode == "copy":
+        dst = torch.empty_like(texts[0])
+        for i in range(args.warmup + args.steps):
+            dst.copy_(texts[i % len(texts)])
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_per_copy": n, "copies": args.warmup + args.steps}))
+        return
     # size the key buffer with one blocking scan
     first = pfac.pfac_scan(a, texts[0])
     count = int(first.numel())

@@ -14,6 +14,7 @@
 
 #include "pfac.h"
 #include "pfac_impl.h"
+#include "scan_internal.h"
 
 namespace pfac {
 namespace {
@@ -52,7 +53,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
     if (a->n_pats == 0) {
         t.root_depth = t.root_bits = t.root_base = 0;
         t.filter_k = t.filter_log2 = 0;
-        t.lds_words = t.rank_word = t.filter_word = 0;
+        t.lds_words = t.root_word = t.rank_word = 0;
         a->lds_image.clear();
         return;
     }
@@ -74,33 +75,33 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
         for (uint32_t j = 0; j < a->n_pats; j++) fkeys.push_back(filter_key(P[j], K, t.pack2));
         std::sort(fkeys.begin(), fkeys.end());
         fkeys.erase(std::unique(fkeys.begin(), fkeys.end()), fkeys.end());
-        // about 32 filter bits per distinct prefix, between 8 and 128 Kibit (1-16 KiB)
-        uint64_t want = (uint64_t)fkeys.size() * 32;
+        // about 64 filter bits per distinct prefix, between 8 and 512 Kibit (1-64 KiB)
+        uint64_t want = (uint64_t)fkeys.size() * 64;
         flog2 = 13;
-        while (flog2 < 17 && (1ull << flog2) < want) flog2++;
+        while (flog2 < kMaxFilterLog2 && (1ull << flog2) < want) flog2++;
     }
     t.filter_k = K > D ? K : 0;
     t.filter_log2 = flog2;
-    t.rank_word = root_words;
-    t.filter_word = root_words + rank_words;
     const uint32_t filter_words = flog2 ? (1u << flog2) / 32 : 0;
-    t.lds_words = t.filter_word + filter_words;
+    t.root_word = filter_words;
+    t.rank_word = filter_words + root_words;
+    t.lds_words = t.rank_word + rank_words;
     a->lds_image.assign(t.lds_words, 0);
     uint32_t *img = a->lds_image.data();
+    uint32_t *root = img + t.root_word;
     for (uint32_t j = 0; j < a->n_pats; j++) {
         uint32_t key = root_key(P[j], D, bits);
-        img[key >> 5] |= 1u << (key & 31);
+        root[key >> 5] |= 1u << (key & 31);
     }
     uint16_t *rank = reinterpret_cast<uint16_t *>(img + t.rank_word);
     uint32_t run = 0;
     for (uint32_t w = 0; w < root_words; w++) {
         rank[w] = (uint16_t)run;
-        run += (uint32_t)__builtin_popcount(img[w]);
+        run += (uint32_t)__builtin_popcount(root[w]);
     }
     // every depth-D node is a D-prefix of some pattern (D <= shortest length)
     if (run != a->depth_start[D + 1] - a->depth_start[D]) throw std::bad_alloc();
-    uint32_t *filt = img + t.filter_word;
-    for (uint32_t key : fkeys) bloom_insert(filt, key, flog2);
+    for (uint32_t key : fkeys) filter_insert(img, key, flog2);
 }
 
 }  // namespace

@@ -1,33 +1,36 @@
-// Streaming failure-less scan for gfx950: one persistent kernel per scan, every wave on
-// its own.
+// Failure-less scan for gfx950: a streaming count kernel and a placement kernel.
 //
 // The method is Section 2.3's: every start position walks the goto-only trie until a
 // transition is missing, and reports every pattern whose final state it reaches; nodes
-// are found with Eq. 1. What is particular to this GPU is how positions reach the walk.
+// are found with Eq. 1. What is particular to this GPU is how positions reach the walk
+// and how the matches reach their place in the output.
 //
-//  * Spans. Each wavefront takes kSpan-byte spans of the text in increasing order from
-//    an atomic ticket and streams them in 1 KiB steps: 64 lanes x 16 bytes, one 16-byte
-//    load per lane, the next steps' loads already in flight. No workgroup barrier is
-//    used after the LDS image is loaded, so the waves of a CU overlap each other's
-//    memory latency freely.
+// Count kernel (scan_count), one persistent wave per span at a time, no wave ever
+// waiting on another:
+//  * Spans. The text is cut into kSpan-byte spans; wave g of G takes spans g, g+G, ...
+//    and streams each in 1 KiB steps: 64 lanes x 16 bytes, one 16-byte load per lane,
+//    the next three steps' loads already in flight.
 //  * LDS prefilter. No pattern is shorter than min_len, so a start can only match if its
 //    first k = min(min_len, kmax) symbols begin some pattern. Each lane tests its 16
-//    starts against an LDS bitmap: a blocked Bloom filter (two bits of one 32-bit word
-//    per k-gram), or the root image itself. A clear bit proves there is no match there;
-//    a set bit sends the start to the walk, which decides exactly.
+//    starts against an LDS bitmap: a hashed k-gram filter or the root image itself. A
+//    clear bit proves there is no match there; a set bit sends the start to the walk,
+//    which decides exactly.
 //  * Root image. The top D trie levels are folded into one direct-indexed bitmap over
 //    D-symbol keys (lexicographic), with a rank per 32-bit word: the rank of a key is
 //    its depth-D node's breadth-first index minus the first depth-D index, i.e. Eq. 1's
 //    popcount rule applied to a D-symbol root. Walks start at that node.
 //  * Survivors go to a wave-private LDS queue in position order and are walked 64 at a
-//    time, one per lane, so the dependent node loads of a walk are paid once per 64
-//    survivors. Walks read nodes and text through L2.
-//  * Output. A span's match count is published and its output offset found by
-//    decoupled look-back over earlier spans (one 64-bit word per span, relaxed atomics).
-//    Starts that matched were kept in a wave-private hit queue in position order; they
-//    are walked again and their keys written at their final place, so the output is
-//    sorted by (start, id) with no global sort. When a span has more matching starts
-//    than the hit queue holds, the rest of the span is streamed again in emit mode.
+//    time, one per lane, mostly at the end of the span so walks seldom stall the stream
+//    of text loads. Walks read nodes and text through L2.
+//  * Per span the kernel stores the match count and one record per matching start
+//    (start, first terminal node, number of terminals), up to kHCap records.
+//
+// Placement kernel (place_emit): blocks of kBlockSpans spans, taken by ticket. A block
+// sums its spans' counts, finds its output offset by decoupled look-back over earlier
+// blocks, and writes every match key at its final place from the records, so the
+// output is sorted by (start, id) with no global sort. A start that passed several
+// terminals, and any start of a span with more matching starts than records, is walked
+// again from the root in HBM.
 #include <mutex>
 
 #include "kernels.h"
@@ -38,22 +41,33 @@ namespace pfac {
 namespace {
 
 constexpr uint64_t kFlagAgg = 1, kFlagInc = 2;
-constexpr uint32_t kSpinLimit = 1u << 24;
+// Bound on any device-side wait, in ticks of the 100 MHz real-time counter (2 s).
+constexpr uint64_t kWaitTicks = 200000000ull;
 constexpr uint32_t kNone = 0xffffffffu;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint32_t bcast(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Inclusive prefix sum over the wave.
+// DPP lane moves (register to register, no LDS round trip). Lanes with no source keep 0.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShl1 = 0x130;
+
+// Inclusive prefix sum over the wave: shifts within each 16-lane row, then the row
+// totals carried into the rows above.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += u;
-    }
+    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr2, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr4, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr8, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowBcast15, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowBcast31, 0xc, 0xf, false);
     return v;
+}
+
+// Value of lane + 1 (lane 63 gets 0).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
+    return __builtin_amdgcn_update_dpp(0u, v, kDppWaveShl1, 0xf, 0xf, false);
 }
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
@@ -63,34 +77,17 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 }
 
 // ------------------------------------------------------------------------ the walk
-template <int LAYOUT, bool PACK2, bool SEG>
-struct Walk {
-    const DevTable &t;
-    const uint8_t *__restrict__ text;
-    const uint32_t *img;  // LDS image
+// Result of one walk: how many pattern ids it passed, how many terminals, the first one.
+struct WalkResult {
+    uint32_t cnt, nterm, term0;
+};
 
-    // Node reached from the root image by the D symbols at s, or -1.
-    __device__ __forceinline__ int64_t root(uint64_t s, uint64_t end) const {
-        const uint32_t D = t.root_depth;
-        if (s + D > end) return -1;
-        uint32_t key = 0;
-        if (PACK2) {
-            for (uint32_t i = 0; i < D; i++) {
-                uint32_t c = text[s + i];
-                if (c > 3) return -1;  // a byte outside the 2-bit code space
-                key = (key << 2) | c;
-            }
-        } else {
-            for (uint32_t i = 0; i < D; i++) key = (key << 8) | text[s + i];
-        }
-        const uint32_t w = key >> 5, b = key & 31;
-        const uint32_t word = img[w];
-        if (!((word >> b) & 1u)) return -1;
-        const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + t.rank_word);
-        return (int64_t)t.root_base + rank[w] + __builtin_popcount(word & ((1u << b) - 1u));
-    }
+template <int LAYOUT>
+struct Trie {
+    const DevTable &t;
 
     __device__ __forceinline__ bool is_term(uint32_t q) const { return (t.nodes[q] >> 63) != 0; }
+    __device__ __forceinline__ uint32_t ids(uint32_t q) const { return t.out_first[q + 1] - t.out_first[q]; }
 
     // Child of q on c (Eq. 1), or -1.
     __device__ __forceinline__ int64_t child(uint32_t q, uint32_t c) const {
@@ -111,50 +108,48 @@ struct Walk {
         }
     }
 
-    // Pattern ids on the walk from s (every terminal passed); *nterm = terminals passed.
-    __device__ uint32_t count(uint64_t s, uint64_t end, uint32_t *nterm) const {
-        int64_t r = root(s, end);
-        *nterm = 0;
-        if (r < 0) return 0;
-        uint32_t q = (uint32_t)r, cnt = 0, nt = 0;
-        uint64_t i = s + t.root_depth;
+    // Walk from node q at text position i (end exclusive): count ids of every terminal,
+    // including q itself.
+    __device__ WalkResult walk_from(uint32_t q, const uint8_t *__restrict__ text, uint64_t i, uint64_t end) const {
+        WalkResult r{0, 0, 0};
         for (;;) {
             if (is_term(q)) {
-                cnt += t.out_first[q + 1] - t.out_first[q];
-                nt++;
+                r.cnt += ids(q);
+                r.term0 = r.nterm == 0 ? q : r.term0;
+                r.nterm++;
             }
             if (i >= end) break;
-            int64_t nq = child(q, text[i]);
+            const int64_t nq = child(q, text[i]);
             if (nq < 0) break;
             q = (uint32_t)nq;
             i++;
         }
-        *nterm = nt;
-        return cnt;
+        return r;
     }
 
-    // Write the cnt keys of start s at keys[o ..), sorted by id.
-    __device__ void emit(uint64_t s, uint64_t end, uint64_t *keys, uint64_t o, uint32_t cnt,
-                         uint32_t nterm) const {
-        int64_t r = root(s, end);
-        if (r < 0) return;
-        uint32_t q = (uint32_t)r, k = 0;
-        uint64_t i = s + t.root_depth;
+    // Keys of start s (walk from the root node 0 in HBM) written at keys[o ..), sorted by
+    // id; cnt is the walk's id count. Ids of one terminal are sorted; those of nested
+    // terminals are merged by insertion.
+    __device__ void emit_walk(const uint8_t *__restrict__ text, uint64_t s, uint64_t end, uint64_t *keys,
+                              uint64_t o, uint32_t cnt) const {
         const uint64_t hi = s << 32;
+        uint32_t q = 0, k = 0, nterm = 0;
+        uint64_t i = s;
         for (;;) {
             if (is_term(q)) {
+                nterm++;
                 for (uint32_t x = t.out_first[q]; x < t.out_first[q + 1]; x++) keys[o + k++] = hi | t.out_ids[x];
                 if (k >= cnt) break;
             }
             if (i >= end) break;
-            int64_t nq = child(q, text[i]);
+            const int64_t nq = child(q, text[i]);
             if (nq < 0) break;
             q = (uint32_t)nq;
             i++;
         }
-        if (nterm > 1) {  // several nested patterns: merge their (sorted) id lists
+        if (nterm > 1) {
             for (uint32_t a = 1; a < cnt; a++) {
-                uint64_t v = keys[o + a];
+                const uint64_t v = keys[o + a];
                 uint32_t b = a;
                 while (b > 0 && keys[o + b - 1] > v) {
                     keys[o + b] = keys[o + b - 1];
@@ -163,6 +158,55 @@ struct Walk {
                 keys[o + b] = v;
             }
         }
+    }
+};
+
+// Walk of a survivor in the count kernel: the first D symbols through the LDS root
+// image, the rest through the trie in HBM. The first eight text bytes come from one
+// round of independent loads.
+template <int LAYOUT, bool PACK2>
+struct RootWalk {
+    const DevTable &t;
+    const uint8_t *__restrict__ text;
+    const uint32_t *img;  // LDS image
+
+    __device__ WalkResult count(uint64_t s, uint64_t end) const {
+        const uint32_t D = t.root_depth;
+        if (s + D > end) return WalkResult{0, 0, 0};
+        uint64_t w8 = 0;
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            if (s + i < end) w8 |= (uint64_t)text[s + i] << (8 * i);
+        uint32_t key = 0;
+        for (uint32_t i = 0; i < D; i++) {
+            const uint32_t c = (uint32_t)(w8 >> (8 * i)) & 0xffu;
+            if (PACK2 && c > 3) return WalkResult{0, 0, 0};  // a byte outside the 2-bit codes
+            key = (key << (PACK2 ? 2 : 8)) | c;
+        }
+        const uint32_t wi = key >> 5, b = key & 31;
+        const uint32_t word = img[kLdsRoot + wi];
+        if (!((word >> b) & 1u)) return WalkResult{0, 0, 0};
+        const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + kLdsRank);
+        uint32_t q = t.root_base + rank[wi] + __builtin_popcount(word & ((1u << b) - 1u));
+        // continue with the bytes already loaded, then one load per level
+        const Trie<LAYOUT> T{t};
+        WalkResult r{0, 0, 0};
+        uint64_t i = s + D;
+        for (;;) {
+            if (T.is_term(q)) {
+                r.cnt += T.ids(q);
+                r.term0 = r.nterm == 0 ? q : r.term0;
+                r.nterm++;
+            }
+            if (i >= end) break;
+            const uint32_t d = (uint32_t)(i - s);
+            const uint32_t c = d < 8 ? (uint32_t)(w8 >> (8 * d)) & 0xffu : (uint32_t)text[i];
+            const int64_t nq = T.child(q, c);
+            if (nq < 0) break;
+            q = (uint32_t)nq;
+            i++;
+        }
+        return r;
     }
 };
 
@@ -178,15 +222,18 @@ __device__ __forceinline__ uint64_t packet_end(const uint64_t *__restrict__ offs
     return offsets[lo + 1];
 }
 
-// 16 bytes at p (zero past n); vector load when it is whole and aligned.
-__device__ __forceinline__ uint4 load16(const uint8_t *__restrict__ text, uint64_t p, uint64_t n, bool aligned) {
+// 16 bytes at p; bytes at or past `lim` read as zero (no load at all when p >= lim).
+// Vector load when the 16 bytes are whole and aligned.
+__device__ __forceinline__ uint4 load16(const uint8_t *__restrict__ text, uint64_t p, uint64_t lim, bool aligned) {
     uint4 v;
-    if (aligned && p + 16 <= n) {
+    if (aligned && p + 16 <= lim) {
         v = *reinterpret_cast<const uint4 *>(text + p);
+    } else if (p >= lim) {
+        v = make_uint4(0u, 0u, 0u, 0u);
     } else {
         uint32_t b[16];
 #pragma unroll
-        for (int i = 0; i < 16; i++) b[i] = p + i < n ? text[p + i] : 0u;
+        for (int i = 0; i < 16; i++) b[i] = p + i < lim ? text[p + i] : 0u;
         v.x = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
         v.y = b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24);
         v.z = b[8] | (b[9] << 8) | (b[10] << 16) | (b[11] << 24);
@@ -208,11 +255,17 @@ __device__ __forceinline__ uint32_t pack2x16(uint4 v) {
     return c;
 }
 
-// LDS test of one prefilter key in the blocked Bloom filter: two bits of one word.
-__device__ __forceinline__ uint32_t bloom2(const uint32_t *F, uint32_t key, uint32_t wshift) {
-    const uint32_t h = key * kFilterMul;
-    const uint32_t w = F[h >> wshift];
-    return (w >> ((h >> 6) & 31)) & (w >> ((h >> 11) & 31)) & 1u;
+// One prefilter probe: the filter word's byte offset is the masked high half of
+// key * kFilterMul (the filter sits at LDS offset 0), the bit is key & 31.
+__device__ __forceinline__ uint32_t probe(const uint32_t *img, uint32_t key, uint32_t amask) {
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) +
+                                                          (__umulhi(key, kFilterMul) & amask));
+    return __builtin_amdgcn_ubfe(w, key, 1);
+}
+
+// One direct probe of the root bitmap: bit `key` of the bitmap at `root`.
+__device__ __forceinline__ uint32_t probe_root(const uint32_t *root, uint32_t key) {
+    return __builtin_amdgcn_ubfe(root[key >> 5], key, 1);
 }
 
 // Survivor mask of this lane's 16 starts (bit j = start 16*lane + j of the step).
@@ -224,225 +277,303 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
     uint32_t mask = 0;
     if (!PACK2) {
         const uint32_t d[5] = {cur.x, cur.y, cur.z, cur.w, next_d0};
-        if (t.filter_k) {
-            const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : ((1u << (8 * t.filter_k)) - 1u);
-            const uint32_t wshift = 37 - t.filter_log2;
-            const uint32_t *F = img + t.filter_word;
+        if (t.filter_k == 4) {
+            const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
-                uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
-                mask |= bloom2(F, x & kmask, wshift) << j;
+                const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
+                mask |= probe(img, x, amask) << j;
+            }
+        } else if (t.filter_k) {
+            const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
+            const uint32_t kmask = (1u << (8 * t.filter_k)) - 1u;
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
+                mask |= probe(img, x & kmask, amask) << j;
             }
         } else {
             // root image as the filter: D-byte key, first byte most significant
+            const uint32_t *root = img + kLdsRoot;
             const bool two = t.root_depth == 2;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
-                uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
-                uint32_t key = two ? (((x & 0xffu) << 8) | ((x >> 8) & 0xffu)) : (x & 0xffu);
-                mask |= ((img[key >> 5] >> (key & 31)) & 1u) << j;
+                const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
+                const uint32_t key = two ? (((x & 0xffu) << 8) | ((x >> 8) & 0xffu)) : (x & 0xffu);
+                mask |= probe_root(root, key) << j;
             }
         }
     } else {
+        // window of K symbols at j: the top 2K bits of symbols j..j+15
         const uint32_t K = t.filter_k ? t.filter_k : t.root_depth;
-        const uint32_t kbits = 2 * K;
-        const uint32_t kmask = kbits >= 32 ? 0xffffffffu : ((1u << kbits) - 1u);
-        const uint32_t rs = kbits >= 32 ? 0 : 32 - kbits;
+        const uint32_t rs = 32 - 2 * K;
         if (t.filter_k) {
-            const uint32_t wshift = 37 - t.filter_log2;
-            const uint32_t *F = img + t.filter_word;
+            const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
-                uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;  // symbols j..j+15
-                mask |= bloom2(F, (top >> rs) & kmask, wshift) << j;
+                const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
+                mask |= probe(img, rs >= 32 ? 0u : top >> rs, amask) << j;
             }
         } else {
+            const uint32_t *root = img + kLdsRoot;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
-                uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
-                uint32_t key = (top >> rs) & kmask;
-                mask |= ((img[key >> 5] >> (key & 31)) & 1u) << j;
+                const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
+                mask |= probe_root(root, top >> rs) << j;
             }
         }
     }
     return mask;
 }
 
-enum Mode { kCount = 0, kEmit = 1 };
-
 // Per-wave state of one span (wave-uniform values).
 struct SpanState {
-    uint64_t a;          // first byte of the span
-    uint32_t qlen;       // survivors queued
-    uint32_t nh;         // hits stored
-    uint32_t ovf;        // span-local start of the first hit not stored, or kNone
-    uint64_t my_cnt;     // this lane's share of the span's match count
-    uint64_t run;        // emit: output index of the next key
+    uint64_t a;       // first byte of the span
+    uint32_t span;    // span index
+    uint32_t qlen;    // survivors queued
+    uint32_t nh;      // records stored
+    uint32_t ovf;     // span-local start of the first matching start not recorded, or kNone
+    uint64_t my_cnt;  // this lane's share of the span's match count
 };
 
 template <int LAYOUT, bool PACK2, bool SEG>
 struct Scanner {
     const DevTable &t;
-    Walk<LAYOUT, PACK2, SEG> W;
+    RootWalk<LAYOUT, PACK2> W;
     const uint8_t *__restrict__ text;
     uint64_t n, lim;  // starts >= lim cannot match (too little text left)
     const uint64_t *__restrict__ offsets;
     uint32_t n_packets;
-    uint64_t *__restrict__ keys;
-    uint64_t cap;
-    uint16_t *q;   // survivor queue (span-local starts), kQCap entries
-    uint16_t *hq;  // hit queue, kHCap entries
+    SpanOut so;
+    uint16_t *q;  // survivor queue (span-local starts), kQCap entries
     bool aligned;
 
     __device__ __forceinline__ uint64_t end_of(uint64_t s) const {
         return SEG ? packet_end(offsets, n_packets, s) : n;
     }
 
-    // Walk `cnt` queued survivors from q[first], one per lane.
-    template <int MODE>
+    // Walk `cnt` queued survivors from q[first], one per lane; record the matching ones.
     __device__ void walk_batch(SpanState &S, uint32_t first, uint32_t cnt) {
         const uint32_t lane = lane_id();
         const bool on = lane < cnt;
         const uint32_t sl = on ? q[first + lane] : 0u;
         const uint64_t s = S.a + sl;
-        uint32_t c = 0, nterm = 0;
-        uint64_t end = 0;
-        if (on) {
-            end = end_of(s);
-            c = W.count(s, end, &nterm);
-        }
-        if (MODE == kCount) {
-            S.my_cnt += c;
-            const uint64_t hb = __ballot(c > 0);
-            if (hb && S.ovf == kNone) {
-                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(hb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hb, 0u));
-                const bool store = c > 0 && S.nh + rank < kHCap;
-                if (store) hq[S.nh + rank] = (uint16_t)sl;
-                const uint64_t lost = __ballot(c > 0 && !store);
-                if (lost) S.ovf = bcast(__shfl(sl, (int)__builtin_ctzll(lost), 64));
-                const uint32_t nh = S.nh + (uint32_t)__builtin_popcountll(hb);
-                S.nh = nh < kHCap ? nh : kHCap;
+        WalkResult r{0, 0, 0};
+        if (on) r = W.count(s, end_of(s));
+        S.my_cnt += r.cnt;
+        const uint64_t hb = __ballot(r.cnt > 0);
+        if (hb && S.ovf == kNone) {
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(hb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hb, 0u));
+            const bool store = r.cnt > 0 && S.nh + rank < kHCap;
+            if (store) {
+                const uint32_t nt = r.nterm < 0xffffu ? r.nterm : 0xffffu;
+                so.rec[(size_t)S.span * kHCap + S.nh + rank] = ((uint64_t)r.term0 << 32) | (nt << 16) | sl;
             }
-        } else {
-            const uint32_t inc = wave_incl_scan(c);
-            const uint32_t tot = __shfl(inc, 63, 64);
-            const uint64_t o = S.run + inc - c;
-            if (c && o + c <= cap) W.emit(s, end, keys, o, c, nterm);
-            S.run += tot;
+            const uint64_t lost = __ballot(r.cnt > 0 && !store);
+            if (lost) S.ovf = __builtin_amdgcn_readlane(sl, (int)__builtin_ctzll(lost));
+            const uint32_t nh = S.nh + (uint32_t)__builtin_popcountll(hb);
+            S.nh = nh < kHCap ? nh : kHCap;
         }
     }
 
-    // Stream starts [lo, hi) of the span (lo >= S.a); survivors are walked in MODE.
-    template <int MODE>
-    __device__ void stream(SpanState &S, uint64_t lo, uint64_t hi) {
+    // Walk every full batch of 64 queued survivors; keep the rest (< 64) at the front.
+    __device__ void drain(SpanState &S) {
         const uint32_t lane = lane_id();
-        uint64_t step = lo & ~(uint64_t)(kStep - 1);
-        uint4 cur = load16(text, step + 16 * lane, n, aligned);
-        uint4 nx1 = load16(text, step + kStep + 16 * lane, n, aligned);
-        uint32_t pc = PACK2 ? pack2x16(cur) : 0u;
-        const uint64_t top = hi < lim ? hi : lim;
-        for (; step < hi; step += kStep) {
-            const uint4 nx2 = load16(text, step + 2 * kStep + 16 * lane, n, aligned);
-            // bytes just after this lane's 16: the next lane's, or the next step's lane 0
-            const uint32_t dn = __shfl_down(cur.x, 1, 64);
-            const uint32_t d0n = bcast(__shfl(nx1.x, 0, 64));
-            const uint32_t next_d0 = lane == 63 ? d0n : dn;
-            uint32_t pn = 0, c1 = 0;
-            if (PACK2) {
-                pn = pack2x16(nx1);
-                const uint32_t cn = __shfl_down(pc, 1, 64);
-                const uint32_t p0n = bcast(__shfl(pn, 0, 64));
-                c1 = lane == 63 ? p0n : cn;
-            }
-            uint32_t m = prefilter16<PACK2>(t, W.img, cur, next_d0, pc, c1);
-            // keep starts in [lo, min(hi, lim))
-            const uint64_t s0 = step + 16 * lane;
-            if (s0 + 16 > top) m &= s0 >= top ? 0u : ((1u << (uint32_t)(top - s0)) - 1u);
-            if (s0 < lo) m &= lo >= s0 + 16 ? 0u : ~((1u << (uint32_t)(lo - s0)) - 1u);
-            if (__ballot(m != 0)) {
-                const uint32_t c = __builtin_popcount(m);
-                const uint32_t inc = wave_incl_scan(c);
-                const uint32_t tot = bcast(__shfl(inc, 63, 64));
-                uint32_t at = S.qlen + inc - c;
-                const uint32_t base_local = (uint32_t)(s0 - S.a);
-                while (m) {
-                    const uint32_t j = __builtin_ctz(m);
-                    m &= m - 1;
-                    q[at++] = (uint16_t)(base_local + j);
-                }
-                S.qlen += tot;
-                __builtin_amdgcn_wave_barrier();
-                if (S.qlen >= 64) {
-                    uint32_t done = 0;
-                    while (S.qlen - done >= 64) {
-                        walk_batch<MODE>(S, done, 64);
-                        done += 64;
-                    }
-                    const uint32_t rest = S.qlen - done;
-                    const uint16_t v = lane < rest ? q[done + lane] : 0;
-                    __builtin_amdgcn_wave_barrier();
-                    if (lane < rest) q[lane] = v;
-                    __builtin_amdgcn_wave_barrier();
-                    S.qlen = rest;
-                }
-            }
-            cur = nx1;
-            nx1 = nx2;
-            pc = pn;
+        uint32_t done = 0;
+        while (S.qlen - done >= 64) {
+            walk_batch(S, done, 64);
+            done += 64;
         }
+        if (!done) return;
+        const uint32_t rest = S.qlen - done;
+        const uint16_t v = lane < rest ? q[done + lane] : 0;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) q[lane] = v;
+        __builtin_amdgcn_wave_barrier();
+        S.qlen = rest;
+    }
+
+    // Survivors of one step: append them to the queue in position order. Walks wait
+    // until the queue might not hold another step (or the span ends).
+    __device__ __forceinline__ void take(SpanState &S, uint32_t m, uint32_t sl0) {
+        if (!__ballot(m != 0)) return;
+        const uint32_t c = __builtin_popcount(m);
+        const uint32_t inc = wave_incl_scan(c);
+        const uint32_t tot = __builtin_amdgcn_readlane(inc, 63);
+        if (S.qlen + tot > kQCap) drain(S);  // now qlen < 64 and tot <= 1024
+        uint32_t at = S.qlen + inc - c;
+        while (m) {
+            const uint32_t j = __builtin_ctz(m);
+            m &= m - 1;
+            q[at++] = (uint16_t)(sl0 + j);
+        }
+        S.qlen += tot;
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // Survivor mask of the step at `step` (lane's 16 starts), cut to [S.a, top).
+    __device__ __forceinline__ uint32_t mask_step(const SpanState &S, uint64_t step, uint64_t top, uint4 cur,
+                                                  uint32_t next_d0, uint32_t pc, uint32_t c1, uint32_t *sl0_out) const {
+        const uint32_t lane = lane_id();
+        uint32_t m = prefilter16<PACK2>(t, W.img, cur, next_d0, pc, c1);
+        const uint32_t sl0 = (uint32_t)(step - S.a) + 16 * lane;  // span-local start of bit 0
+        if (step + kStep > top) {  // last step: keep starts below top
+            const uint64_t s0 = S.a + sl0;
+            if (s0 + 16 > top) m &= s0 >= top ? 0u : ((1u << (uint32_t)(top - s0)) - 1u);
+        }
+        *sl0_out = sl0;
+        return m;
+    }
+
+    // Count the span [S.a, hi).
+    __device__ void stream(SpanState &S, uint64_t hi) {
+        const uint32_t lane = lane_id();
+        uint64_t step = S.a;
+        const uint64_t hiR = (hi + kStep - 1) & ~(uint64_t)(kStep - 1);  // end of the last step
+        const uint64_t top = hi < lim ? hi : lim;
+        if (aligned && hiR + 16 <= n) {
+            // Steady state: every load is an unconditional 16-byte load with no per-lane
+            // test, three steps ahead; addresses past the span are clamped to its last
+            // step (a repeated load, no bytes past the span). Only the 16 bytes right
+            // after the span are read for the last starts' windows.
+            const uint64_t lastst = hiR - kStep;
+            const uint4 tail = *reinterpret_cast<const uint4 *>(text + hiR);  // uniform address
+            uint4 cur = *reinterpret_cast<const uint4 *>(text + step + 16 * lane);
+            uint4 nx1 = *reinterpret_cast<const uint4 *>(text + (step + kStep < lastst ? step + kStep : lastst) + 16 * lane);
+            uint4 nx2 = *reinterpret_cast<const uint4 *>(text + (step + 2 * kStep < lastst ? step + 2 * kStep : lastst) + 16 * lane);
+            uint32_t pc = PACK2 ? pack2x16(cur) : 0u;
+            const uint32_t ptail = PACK2 ? pack2x16(tail) : 0u;
+            for (; step < hiR; step += kStep) {
+                const uint64_t a3 = step + 3 * kStep < lastst ? step + 3 * kStep : lastst;
+                const uint4 nx3 = *reinterpret_cast<const uint4 *>(text + a3 + 16 * lane);
+                const bool last = step == lastst;
+                const uint32_t dn = from_next_lane(cur.x);
+                const uint32_t d0n = last ? tail.x : __builtin_amdgcn_readfirstlane(nx1.x);
+                const uint32_t next_d0 = lane == 63 ? d0n : dn;
+                uint32_t pn = 0, c1 = 0;
+                if (PACK2) {
+                    pn = pack2x16(nx1);
+                    const uint32_t cn = from_next_lane(pc);
+                    const uint32_t p0n = last ? ptail : __builtin_amdgcn_readfirstlane(pn);
+                    c1 = lane == 63 ? p0n : cn;
+                }
+                uint32_t sl0;
+                const uint32_t m = mask_step(S, step, top, cur, next_d0, pc, c1, &sl0);
+                take(S, m, sl0);
+                cur = nx1;
+                nx1 = nx2;
+                nx2 = nx3;
+                pc = pn;
+            }
+        } else {
+            // End of the text, or an unaligned text: guarded loads, zero past the end.
+            const uint64_t need = hi + (PACK2 ? 16 : 4);
+            const uint64_t ld = need < n ? need : n;
+            uint4 cur = load16(text, step + 16 * lane, ld, aligned);
+            uint4 nx1 = load16(text, step + kStep + 16 * lane, ld, aligned);
+            uint32_t pc = PACK2 ? pack2x16(cur) : 0u;
+            for (; step < hi; step += kStep) {
+                const uint4 nx2 = load16(text, step + 2 * kStep + 16 * lane, ld, aligned);
+                const uint32_t dn = from_next_lane(cur.x);
+                const uint32_t d0n = __builtin_amdgcn_readfirstlane(nx1.x);
+                const uint32_t next_d0 = lane == 63 ? d0n : dn;
+                uint32_t pn = 0, c1 = 0;
+                if (PACK2) {
+                    pn = pack2x16(nx1);
+                    const uint32_t cn = from_next_lane(pc);
+                    const uint32_t p0n = __builtin_amdgcn_readfirstlane(pn);
+                    c1 = lane == 63 ? p0n : cn;
+                }
+                uint32_t sl0;
+                const uint32_t m = mask_step(S, step, top, cur, next_d0, pc, c1, &sl0);
+                take(S, m, sl0);
+                cur = nx1;
+                nx1 = nx2;
+                pc = pn;
+            }
+        }
+        drain(S);
         if (S.qlen) {
-            walk_batch<MODE>(S, 0, S.qlen);
+            walk_batch(S, 0, S.qlen);
             S.qlen = 0;
         }
     }
 };
 
-// ------------------------------------------------------------------------ kernel
+// ------------------------------------------------------------------ count kernel
 template <int LAYOUT, bool PACK2, bool SEG>
-__global__ __launch_bounds__(kThreads) void scan_stream(DevTable t, const uint8_t *__restrict__ text,
-                                                       uint64_t n, const uint64_t *__restrict__ offsets,
-                                                       uint32_t n_packets, uint64_t *__restrict__ keys,
-                                                       uint64_t cap, uint64_t *__restrict__ d_count,
-                                                       TileState ts, uint32_t n_spans) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint32_t *img = reinterpret_cast<uint32_t *>(smem);
-    for (uint32_t i = threadIdx.x; i < t.lds_words; i += kThreads) img[i] = t.lds_image[i];
-    __syncthreads();  // the only workgroup barrier: waves run independently from here
+__global__ __launch_bounds__(kThreads) void scan_count(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
+                                                      const uint64_t *__restrict__ offsets, uint32_t n_packets,
+                                                      SpanOut so, uint32_t n_spans) {
+    __shared__ __align__(16) uint32_t img[kLdsWords];
+    {
+        // filter words to offset 0, root bitmap and rank table to their fixed places
+        const uint32_t fw = t.root_word, rw = t.rank_word - t.root_word, kw = t.lds_words - t.rank_word;
+        for (uint32_t i = threadIdx.x; i < fw; i += kThreads) img[i] = t.lds_image[i];
+        for (uint32_t i = threadIdx.x; i < rw; i += kThreads) img[kLdsRoot + i] = t.lds_image[fw + i];
+        for (uint32_t i = threadIdx.x; i < kw; i += kThreads) img[kLdsRank + i] = t.lds_image[fw + rw + i];
+    }
+    __syncthreads();  // the only barrier: waves run independently from here
 
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    uint16_t *wq = reinterpret_cast<uint16_t *>(smem + image_bytes(t) + wave * kWaveLds);
-    Scanner<LAYOUT, PACK2, SEG> sc{t, {t, text, img}, text, n,
-                                   n >= t.min_len ? n - t.min_len + 1 : 0,
-                                   offsets, n_packets, keys, cap, wq, wq + kQCap,
-                                   (((uintptr_t)text) & 15) == 0};
-    uint32_t epoch = 0;
-    if (lane == 0) epoch = __hip_atomic_load(&ts.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    epoch = bcast(epoch);
-    const uint64_t tagE = (uint64_t)epoch << 44;
-
-    for (;;) {
-        uint32_t span = 0;
-        if (lane == 0) span = __hip_atomic_fetch_add(&ts.ctrl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        span = bcast(span);
-        if (span >= n_spans) break;
-        SpanState S{(uint64_t)span * kSpan, 0, 0, kNone, 0, 0};
-        const uint64_t b = S.a + kSpan < n ? S.a + kSpan : n;
-        sc.template stream<kCount>(S, S.a, b);
+    uint16_t *wq = reinterpret_cast<uint16_t *>(img + kLdsQueues) + wave * kQCap;
+    Scanner<LAYOUT, PACK2, SEG> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
+                                   offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0};
+    const uint32_t waves = gridDim.x * kWaves;
+    for (uint32_t span = blockIdx.x * kWaves + wave; span < n_spans; span += waves) {
+        SpanState S{(uint64_t)span * kSpan, span, 0, 0, kNone, 0};
+        const uint64_t hi = S.a + kSpan < n ? S.a + kSpan : n;
+        sc.stream(S, hi);
         const uint64_t total = wave_sum64(S.my_cnt);
+        if (lane == 0) {
+            so.cnt[span] = total;
+            so.nh[span] = S.nh;
+            so.ovf[span] = S.ovf;
+        }
+    }
+}
 
-        // publish the span's count; find its output offset by decoupled look-back
+// ------------------------------------------------------------------ placement kernel
+template <int LAYOUT, bool SEG>
+__global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
+                                                           const uint64_t *__restrict__ offsets, uint32_t n_packets,
+                                                           uint64_t *__restrict__ keys, uint64_t cap,
+                                                           uint64_t *__restrict__ d_count, SpanOut so, TileState ts,
+                                                           uint32_t n_spans, uint32_t n_blocks) {
+    __shared__ uint64_t span_off[kBlockSpans];
+    __shared__ uint32_t sh[4];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const Trie<LAYOUT> T{t};
+    if (threadIdx.x == 0) {
+        sh[0] = __hip_atomic_fetch_add(&ts.ctrl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh[1] = __hip_atomic_load(&ts.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t blk = sh[0], epoch = sh[1];
+    const uint64_t tagE = (uint64_t)epoch << 44;
+    if (blk < n_blocks && wave == 0) {
+        // the block's span counts, their prefix, and the block's place by look-back
+        const uint32_t sp = blk * kBlockSpans + lane;
+        const uint64_t c = sp < n_spans ? so.cnt[sp] : 0;
+        uint64_t inc = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t u = __shfl_up(inc, d, 64);
+            if (lane >= (uint32_t)d) inc += u;
+        }
+        const uint64_t total = __shfl(inc, 63, 64);
         if (lane == 0) {
             const uint64_t v = total > kValueMask ? kValueMask : total;
-            __hip_atomic_store(&ts.word[span], tagE | ((span == 0 ? kFlagInc : kFlagAgg) << 42) | v,
+            __hip_atomic_store(&ts.word[blk], tagE | ((blk == 0 ? kFlagInc : kFlagAgg) << 42) | v,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         uint64_t excl = 0;
-        if (span > 0) {
-            int64_t j = (int64_t)span - 1;
-            uint32_t spins = 0;
+        if (blk > 0) {
+            int64_t j = (int64_t)blk - 1;
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
             for (;;) {
                 const int64_t idx = j - (int64_t)lane;
-                uint64_t wd = tagE | (kFlagInc << 42);  // before span 0: prefix 0
+                uint64_t wd = tagE | (kFlagInc << 42);  // before block 0: prefix 0
                 if (idx >= 0) wd = __hip_atomic_load(&ts.word[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t flag = (uint32_t)(wd >> 42) & 3u;
                 const bool ready = (wd >> 44) == epoch && flag != 0;
@@ -451,7 +582,7 @@ __global__ __launch_bounds__(kThreads) void scan_stream(DevTable t, const uint8_
                 const uint32_t first = incm ? (uint32_t)__builtin_ctzll(incm) : 64u;
                 const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
                 if (__ballot(!ready) & need) {
-                    if (++spins > kSpinLimit) {  // never expected; report, don't hang
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {  // never expected
                         if (lane == 0) {
                             __hip_atomic_fetch_or(&ts.ctrl[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -466,53 +597,84 @@ __global__ __launch_bounds__(kThreads) void scan_stream(DevTable t, const uint8_
                 j -= 64;
             }
             if (lane == 0) {
-                uint64_t inc = excl + total;
-                if (inc > kValueMask) {
+                uint64_t v = excl + total;
+                if (v > kValueMask) {
                     __hip_atomic_fetch_or(&ts.ctrl[3], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    inc = kValueMask;
+                    v = kValueMask;
                 }
-                __hip_atomic_store(&ts.word[span], tagE | (kFlagInc << 42) | inc, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ts.word[blk], tagE | (kFlagInc << 42) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-
-        // emit: stored hits in position order, then (if the hit queue overflowed) the
-        // rest of the span streamed again in emit mode
-        if (total) {
-            S.run = excl;
-            for (uint32_t h0 = 0; h0 < S.nh; h0 += 64) {
-                const uint32_t cnt = S.nh - h0 < 64 ? S.nh - h0 : 64;
-                // walk_batch reads its starts from q: move this batch of hits there
-                const uint16_t v = lane < cnt ? sc.hq[h0 + lane] : 0;
-                __builtin_amdgcn_wave_barrier();
-                if (lane < cnt) sc.q[lane] = v;
-                __builtin_amdgcn_wave_barrier();
-                sc.template walk_batch<kEmit>(S, 0, cnt);
-                __builtin_amdgcn_wave_barrier();
+        span_off[lane] = excl + inc - c;
+    }
+    __syncthreads();
+    if (blk < n_blocks) {
+        // each wave writes the keys of every kPlaceWaves-th span of the block
+        for (uint32_t i = wave; i < kBlockSpans; i += kPlaceWaves) {
+            const uint32_t sp = blk * kBlockSpans + i;
+            if (sp >= n_spans || so.cnt[sp] == 0) continue;
+            uint64_t run = span_off[i];
+            const uint64_t a = (uint64_t)sp * kSpan;
+            const uint64_t b = a + kSpan < n ? a + kSpan : n;
+            const uint32_t nh = so.nh[sp], ovf = so.ovf[sp];
+            for (uint32_t h0 = 0; h0 < nh; h0 += 64) {
+                const bool on = h0 + lane < nh;
+                uint64_t rec = on ? so.rec[(size_t)sp * kHCap + h0 + lane] : 0;
+                const uint64_t s = a + (rec & 0xffffu);
+                const uint32_t nterm = (uint32_t)(rec >> 16) & 0xffffu, q0 = (uint32_t)(rec >> 32);
+                const uint64_t end = on ? (SEG ? packet_end(offsets, n_packets, s) : n) : 0;
+                uint32_t c = 0;
+                if (on) c = nterm == 1 ? T.ids(q0) : T.walk_from(0, text, s, end).cnt;
+                const uint32_t incl = wave_incl_scan(c);
+                const uint64_t o = run + incl - c;
+                if (c && o + c <= cap) {
+                    if (nterm == 1) {
+                        const uint64_t hi = s << 32;
+                        const uint32_t f = t.out_first[q0];
+                        for (uint32_t x = 0; x < c; x++) keys[o + x] = hi | t.out_ids[f + x];
+                    } else {
+                        T.emit_walk(text, s, end, keys, o, c);
+                    }
+                }
+                run += __builtin_amdgcn_readlane(incl, 63);
             }
-            if (S.ovf != kNone) sc.template stream<kEmit>(S, S.a + S.ovf, b);
+            if (ovf != kNone) {
+                // more matching starts than records: walk every start from the first one
+                // not recorded, 64 at a time, from the root in HBM
+                const uint64_t lim = n >= t.min_len ? n - t.min_len + 1 : 0;
+                const uint64_t top = b < lim ? b : lim;
+                for (uint64_t s0 = a + ovf; s0 < top; s0 += 64) {
+                    const uint64_t s = s0 + lane;
+                    const bool on = s < top;
+                    const uint64_t end = on ? (SEG ? packet_end(offsets, n_packets, s) : n) : 0;
+                    const uint32_t c = on ? T.walk_from(0, text, s, end).cnt : 0;
+                    const uint32_t incl = wave_incl_scan(c);
+                    const uint64_t o = run + incl - c;
+                    if (c && o + c <= cap) T.emit_walk(text, s, end, keys, o, c);
+                    run += __builtin_amdgcn_readlane(incl, 63);
+                }
+            }
         }
     }
-
-    // last wave out: writes the count, resets the ticket, advances the epoch
-    if (lane == 0) {
-        const uint32_t waves = gridDim.x * (kThreads / 64);
+    // last workgroup out: writes the count, resets the ticket, advances the epoch
+    __syncthreads();
+    if (threadIdx.x == 0) {
         const uint32_t done = __hip_atomic_fetch_add(&ts.ctrl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (done == waves - 1) {
+        if (done == gridDim.x - 1) {
             uint64_t total = 0;
-            if (n_spans) {
-                // the last span's inclusive prefix: every span is published by now, so
+            if (n_blocks) {
+                // the last block's inclusive prefix: every block is published by now, so
                 // this wait ends as soon as the word is visible
                 const uint64_t want = tagE | (kFlagInc << 42);
-                uint32_t spins = 0;
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
                 for (;;) {
-                    const uint64_t wd = __hip_atomic_load(&ts.word[n_spans - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint64_t wd = __hip_atomic_load(&ts.word[n_blocks - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if ((wd & ~kValueMask) == want) {
                         total = wd & kValueMask;
                         break;
                     }
-                    if (++spins > kSpinLimit) {
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
                         __hip_atomic_fetch_or(&ts.ctrl[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
@@ -533,49 +695,46 @@ __global__ __launch_bounds__(kThreads) void scan_stream(DevTable t, const uint8_
 }
 
 template <int LAYOUT, bool PACK2, bool SEG>
-int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets,
-               uint32_t n_packets, uint64_t *keys, uint64_t cap, uint64_t *d_count,
-               const TileState &ts, uint32_t grid, hipStream_t s) {
+int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
+               uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
+               uint32_t grid, hipStream_t s) {
     const uint32_t n_spans = (uint32_t)((n + kSpan - 1) / kSpan);
-    const size_t lds = scan_lds_bytes(t);
-    auto k = scan_stream<LAYOUT, PACK2, SEG>;
-    // allow up to the whole 160 KiB of LDS, once per kernel (an attribute call per launch
-    // costs far more than the launch itself)
+    const uint32_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
+    auto k = scan_count<LAYOUT, PACK2, SEG>;
     static std::once_flag once;
     static int cus = 0;
+    static int per_cu = 1;
     std::call_once(once, [&] {
-        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         int dev = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (cus <= 0) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
     });
     if (grid == 0) {
-        // as many workgroups as can be resident at once, and no more than it takes to
-        // give every wave a span
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, lds) != hipSuccess || per_cu < 1)
-            per_cu = 1;
-        uint64_t g = (uint64_t)cus * (uint32_t)per_cu;
+        // as many workgroups as are resident at once, no more than it takes to give
+        // every wave a span
+        const uint64_t g = (uint64_t)cus * (uint32_t)per_cu;
         const uint64_t need = (n_spans + kWaves - 1) / kWaves;
         grid = (uint32_t)(g < need ? g : need);
         if (grid == 0) grid = 1;
     }
-    k<<<grid, kThreads, lds, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count, ts, n_spans);
+    k<<<grid, kThreads, 0, s>>>(t, text, n, offsets, n_packets, so, n_spans);
+    place_emit<LAYOUT, SEG><<<n_blocks, kPlaceThreads, 0, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count,
+                                                                so, ts, n_spans, n_blocks);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
 
-size_t scan_lds_bytes(const DevTable &t) { return image_bytes(t) + (size_t)kWaves * kWaveLds; }
-
-int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets,
-                 uint32_t n_packets, uint64_t *keys, uint64_t cap, uint64_t *d_count,
-                 const TileState &ts, uint32_t grid, hipStream_t s) {
+int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
+                 uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
+                 uint32_t grid, hipStream_t s) {
     const bool seg = offsets != nullptr;
     const bool narrow = t.layout == LAYOUT_NARROW;
     const bool pack2 = t.pack2 != 0;
-#define PFAC_L(LA, P2, SG) return launch_one<LA, P2, SG>(t, text, n, offsets, n_packets, keys, cap, d_count, ts, grid, s)
+#define PFAC_L(LA, P2, SG) return launch_one<LA, P2, SG>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, grid, s)
     if (narrow) {
         if (pack2) { if (seg) PFAC_L(LAYOUT_NARROW, true, true); else PFAC_L(LAYOUT_NARROW, true, false); }
         else { if (seg) PFAC_L(LAYOUT_NARROW, false, true); else PFAC_L(LAYOUT_NARROW, false, false); }

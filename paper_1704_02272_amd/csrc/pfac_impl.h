@@ -33,9 +33,9 @@ constexpr uint32_t kMaxPatternLen = 1u << 24;
 constexpr uint32_t kMaxNodes = 0x7fffffffu;
 
 // Per-workgroup LDS image (copied from HBM at kernel start), in 32-bit words:
+//   [filter: 2^filter_log2 bits]         k-gram prefix filter (optional), at offset 0
 //   [root bitmap: 2^root_bits bits]      D-gram -> present?   (D = root_depth)
 //   [root rank: 2^(root_bits-5) u16]     set bits before each 32-bit word
-//   [filter: 2^filter_log2 bits]         blocked Bloom filter of k-gram prefixes (optional)
 // The root image folds the top D trie levels into one direct-indexed bitmap whose rank
 // (the popcount rule of Eq. 1 applied to a D-symbol root) is the breadth-first index of
 // the depth-D node: node = depth_start[D] + rank(key), keys in lexicographic order.
@@ -57,19 +57,22 @@ struct DevTable {
     uint32_t filter_k;          // k (symbols per filter key); 0 = no hashed filter
     uint32_t filter_log2;       // log2(filter bits)
     uint32_t lds_words;         // total image size in 32-bit words
+    uint32_t root_word;         // word offset of the root bitmap
     uint32_t rank_word;         // word offset of the rank table
-    uint32_t filter_word;       // word offset of the filter
 };
 
 constexpr uint32_t kFilterMul = 0x9E3779B1u;  // multiplicative hash (golden ratio)
 
-// Blocked Bloom filter over k-gram keys, 2^log2_bits bits (log2_bits in 13..21): a key
-// sets two bits of one 32-bit word. h = key * kFilterMul; word = the top log2_bits - 5
-// bits of h; bits (h >> 6) & 31 and (h >> 11) & 31. The builder and the kernels must
-// agree bit for bit.
-inline void bloom_insert(uint32_t *F, uint32_t key, uint32_t log2_bits) {
-    const uint32_t h = key * kFilterMul;
-    F[h >> (37 - log2_bits)] |= (1u << ((h >> 6) & 31)) | (1u << ((h >> 11) & 31));
+// Prefilter over k-gram keys, 2^log2_bits bits (log2_bits in 13..22): a key sets one
+// bit. Word = bits 2.. of the high half of key * kFilterMul (masked to the word count),
+// so the masked high half is directly the word's byte offset; bit = key & 31. The
+// builder and the kernels must agree bit for bit.
+__host__ __device__ inline uint32_t filter_byte_offset(uint32_t key, uint32_t log2_bits) {
+    const uint32_t hi = (uint32_t)(((uint64_t)key * kFilterMul) >> 32);
+    return hi & (((1u << (log2_bits - 5)) - 1u) << 2);
+}
+inline void filter_insert(uint32_t *F, uint32_t key, uint32_t log2_bits) {
+    F[filter_byte_offset(key, log2_bits) >> 2] |= 1u << (key & 31);
 }
 
 struct Workspace;  // per (device, stream) scratch, defined in the runtime

@@ -15,9 +15,11 @@ struct Workspace {
     int device = -1;
     uint64_t cap_blocks = 0;  // plain scan: per-block counts and offsets
     uint64_t *block_counts = nullptr, *block_offsets = nullptr;
-    uint64_t cap_tiles = 0;   // tiled scan: look-back state
+    uint64_t cap_spans = 0;   // tiled scan: per-span results
+    SpanOut so{};
+    uint64_t cap_tiles = 0;   // tiled scan: look-back words (one per placement block)
     TileState ts{};
-    uint64_t launches = 0;    // tiled launches since the tile words were last cleared
+    uint64_t launches = 0;    // tiled launches since the look-back words were last cleared
     uint64_t *d_count = nullptr;  // count for the blocking scan
     uint64_t *h_count = nullptr;  // pinned host mirror
 };
@@ -51,6 +53,12 @@ void free_tiles(Workspace *w) {
     hipFree(w->ts.ctrl);
     w->ts = TileState{};
     w->cap_tiles = 0;
+    hipFree(w->so.cnt);
+    hipFree(w->so.nh);
+    hipFree(w->so.ovf);
+    hipFree(w->so.rec);
+    w->so = SpanOut{};
+    w->cap_spans = 0;
 }
 
 __global__ void clear_tiles_kernel(uint64_t *word, uint64_t n, uint32_t *ctrl) {
@@ -146,14 +154,20 @@ static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo,
             return PFAC_ENOMEM;
     }
     if (algo == PFAC_ALGO_TILED) {
-        uint64_t nt = (n + kSpan - 1) / kSpan;
-        if (nt > w->cap_tiles || !w->ts.ctrl) {
+        const uint64_t ns = (n + kSpan - 1) / kSpan;
+        if (ns > w->cap_spans || !w->ts.ctrl) {
             if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
             free_tiles(w);
-            uint64_t want = nt < 4096 ? 4096 : nt + nt / 4;
-            if (hipMalloc(&w->ts.word, want * 8) != hipSuccess) return PFAC_ENOMEM;
+            const uint64_t spans = ns < 1024 ? 1024 : ns + ns / 4;
+            const uint64_t blocks = (spans + kBlockSpans - 1) / kBlockSpans;
+            if (hipMalloc(&w->so.cnt, spans * 8) != hipSuccess) return PFAC_ENOMEM;
+            if (hipMalloc(&w->so.nh, spans * 4) != hipSuccess) return PFAC_ENOMEM;
+            if (hipMalloc(&w->so.ovf, spans * 4) != hipSuccess) return PFAC_ENOMEM;
+            if (hipMalloc(&w->so.rec, spans * kHCap * 8) != hipSuccess) return PFAC_ENOMEM;
+            if (hipMalloc(&w->ts.word, blocks * 8) != hipSuccess) return PFAC_ENOMEM;
             if (hipMalloc(&w->ts.ctrl, 16) != hipSuccess) return PFAC_ENOMEM;
-            w->cap_tiles = want;
+            w->cap_spans = spans;
+            w->cap_tiles = blocks;
             w->launches = kEpochPeriod;  // forces a clear before the first launch
         }
         if (w->launches >= kEpochPeriod) {
@@ -228,9 +242,9 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, ui
             return PFAC_EHIP;
         return PFAC_OK;
     }
-    const uint64_t nt = (n + kSpan - 1) / kSpan;
-    const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, nt) : 0u;
-    if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, cnt, w->ts, grid, s))
+    const uint64_t ns = (n + kSpan - 1) / kSpan;
+    const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, (ns + kWaves - 1) / kWaves) : 0u;
+    if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, cnt, w->so, w->ts, grid, s))
         return PFAC_EHIP;
     w->launches++;
     return PFAC_OK;

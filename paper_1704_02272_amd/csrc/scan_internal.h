@@ -12,22 +12,47 @@ constexpr uint32_t kThreads = 1024;  // workgroup: 16 waves sharing one LDS imag
 constexpr uint32_t kWaves = kThreads / 64;
 constexpr uint32_t kStep = 1024;     // bytes a wave streams per step: 64 lanes x 16
 constexpr uint32_t kSpan = 16384;    // bytes per work unit (a wave's ticket)
-constexpr uint32_t kQCap = 1088;     // survivor queue: 63 left over + a whole step
-constexpr uint32_t kHCap = 256;      // hit queue (starts with a match) per span
-constexpr uint32_t kWaveLds = (kQCap + kHCap) * 2;  // bytes of LDS per wave
+constexpr uint32_t kQCap = 2048;     // survivor queue; walked when a step might not fit, and at the span end
+constexpr uint32_t kHCap = 256;      // match records kept per span
+constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
+constexpr uint32_t kPlaceThreads = 256;
+constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
+constexpr uint32_t kWaveLds = kQCap * 2;  // bytes of LDS per wave (survivor queue)
 static_assert(kSpan <= 65536, "span-local starts are 16-bit");
 static_assert(kWaveLds % 16 == 0, "wave regions stay 16-byte aligned");
 
-__host__ __device__ inline size_t image_bytes(const DevTable &t) { return ((size_t)t.lds_words * 4 + 15) & ~(size_t)15; }
+// Fixed LDS layout of the scan kernel (32-bit words): the filter at offset 0 so a probe's
+// masked hash is its byte address, then the root bitmap and its rank table, then the
+// per-wave queues. Compile-time offsets fold into the LDS instructions.
+constexpr uint32_t kFilterWordsMax = 1u << 14;  // 64 KiB: filters up to 2^19 bits
+constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
+constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
+constexpr uint32_t kLdsRoot = kFilterWordsMax;
+constexpr uint32_t kLdsRank = kLdsRoot + kRootWordsMax;
+constexpr uint32_t kLdsQueues = kLdsRank + kRankWordsMax;
+constexpr uint32_t kLdsWords = kLdsQueues + kWaves * kWaveLds / 4;
+constexpr uint32_t kMaxFilterLog2 = 19;
 
-// Decoupled look-back state of one scan (device memory, owned by a workspace).
-//   word[t]   one 64-bit word per span: epoch (bits 44..63) | flag (42..43) | value (0..41)
-//             flag 1: value = matches in span t; flag 2: value = matches in spans 0..t.
+// Per-span results of the count kernel (device memory, owned by a workspace).
+//   cnt[s]   matches in span s          nh[s]   records stored for span s
+//   ovf[s]   span-local start of the first matching start without a record, or ~0
+//   rec[s * kHCap + i]   record i: first terminal node (bits 32..63) | terminals passed
+//                        (16..31, saturated) | span-local start (0..15)
+struct SpanOut {
+    uint64_t *cnt;
+    uint32_t *nh;
+    uint32_t *ovf;
+    uint64_t *rec;
+};
+
+// Decoupled look-back state of the placement kernel (device memory, in a workspace).
+//   word[b]   one 64-bit word per block: epoch (bits 44..63) | flag (42..43) | value (0..41)
+//             flag 1: value = matches in block b; flag 2: value = matches in blocks 0..b.
 //             Flag and value share one word, so publishing and reading need only relaxed
 //             device-scope atomics: no fence, no L2 write-back or invalidate per tile.
-//   ctrl[0]   span ticket   ctrl[1] waves done   ctrl[2] epoch (1 .. 2^20 - 1)
+//   ctrl[0]   block ticket   ctrl[1] workgroups done   ctrl[2] epoch (1 .. 2^20 - 1)
 //   ctrl[3]   error bits (1: a bounded wait expired, 2: count past 2^42)
-// The last wave of a launch writes the count, resets the ticket and the done count
+// The last workgroup of a launch writes the count, resets the ticket and the done count
 // and advances the epoch, so a later launch (or a replayed graph) needs no host-side
 // reset; words of an older epoch never match. The host clears the words before the epoch
 // could wrap (kEpochPeriod launches).
@@ -43,10 +68,10 @@ struct TileState {
 constexpr uint64_t kCountTimeout = ~0ull;
 constexpr uint64_t kCountOverflow = ~0ull - 1;
 
-size_t scan_lds_bytes(const DevTable &t);
-// grid = 0: as many workgroups as fit on the device at once.
-int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets,
-                 uint32_t n_packets, uint64_t *keys, uint64_t cap, uint64_t *d_count,
-                 const TileState &ts, uint32_t grid, hipStream_t s);
+// Count kernel then placement kernel on stream s. grid: workgroups of the count kernel
+// (0 = as many as are resident at once).
+int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
+                 uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
+                 uint32_t grid, hipStream_t s);
 
 }  // namespace pfac
