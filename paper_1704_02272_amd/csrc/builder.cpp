@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 
 #include "pfac.h"
@@ -52,46 +53,74 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
     const uint32_t bits = t.pack2 ? 2 : 8;
     if (a->n_pats == 0) {
         t.root_depth = t.root_bits = t.root_base = 0;
-        t.filter_k = t.filter_log2 = 0;
-        t.lds_words = t.root_word = t.rank_word = 0;
+        t.filter_k = t.filter_log2 = t.has_short = 0;
+        t.lds_words = t.root_word = t.rank_word = t.short_word = 0;
         a->lds_image.clear();
         return;
     }
     const uint32_t dmax = t.pack2 ? 8 : 2;
     const uint32_t kmax = t.pack2 ? 16 : 4;
     const uint32_t D = std::min(a->min_len, dmax);
-    const uint32_t K = std::min(a->min_len, kmax);
     t.root_depth = D;
     t.root_bits = D * bits;
     t.root_base = a->depth_start[D];
     const uint32_t root_nbits = 1u << t.root_bits;
     const uint32_t root_words = std::max<uint32_t>(1, root_nbits / 32);
-    const uint32_t rank_entries = root_words;  // one u16 per 32-bit word
-    const uint32_t rank_words = (rank_entries + 1) / 2;
+    const uint32_t rank_words = (root_words + 1) / 2;  // one u16 per root word
+    // Filter key length K: patterns of length >= K are tested by their K-gram in the
+    // hashed filter, shorter ones by their D-gram in the short bitmap. K minimizes the
+    // estimated pass rate on uniform text: the short D-grams' share of all D-grams, plus
+    // the long K-grams' false-positive share of the filter bits (one bit per key), plus
+    // their true share of all K-grams. Ties go to the longer key.
+    const uint32_t kcap = std::min(kmax, a->max_len);
+    uint32_t K = D;
+    double best = 1e30;
+    for (uint32_t k = D; k <= kcap; k++) {
+        std::vector<uint32_t> sk, lk;
+        for (uint32_t j = 0; j < a->n_pats; j++) {
+            if (a->pat_len[j] < k) sk.push_back(root_key(P[j], D, bits));
+            else lk.push_back(filter_key(P[j], k, t.pack2));
+        }
+        std::sort(sk.begin(), sk.end());
+        sk.erase(std::unique(sk.begin(), sk.end()), sk.end());
+        std::sort(lk.begin(), lk.end());
+        lk.erase(std::unique(lk.begin(), lk.end()), lk.end());
+        const double space = std::pow((double)a->alphabet, (double)k);
+        double est = (double)sk.size() / root_nbits + (double)lk.size() / space;
+        if (k > D) est += (double)lk.size() / (double)(1u << kMaxFilterLog2);
+        if (est <= best * 1.001) {
+            best = est;
+            K = k;
+        }
+    }
     uint32_t flog2 = 0;
     std::vector<uint32_t> fkeys;
+    bool any_short = false;
     if (K > D) {
-        fkeys.reserve(a->n_pats);
-        for (uint32_t j = 0; j < a->n_pats; j++) fkeys.push_back(filter_key(P[j], K, t.pack2));
+        for (uint32_t j = 0; j < a->n_pats; j++) {
+            if (a->pat_len[j] >= K) fkeys.push_back(filter_key(P[j], K, t.pack2));
+            else any_short = true;
+        }
         std::sort(fkeys.begin(), fkeys.end());
         fkeys.erase(std::unique(fkeys.begin(), fkeys.end()), fkeys.end());
-        // about 64 filter bits per distinct prefix, between 8 and 512 Kibit (1-64 KiB)
-        uint64_t want = (uint64_t)fkeys.size() * 64;
-        flog2 = 13;
-        while (flog2 < kMaxFilterLog2 && (1ull << flog2) < want) flog2++;
+        flog2 = kMaxFilterLog2;  // its LDS is reserved in any case: take all of it
     }
     t.filter_k = K > D ? K : 0;
     t.filter_log2 = flog2;
+    t.has_short = any_short ? 1 : 0;
     const uint32_t filter_words = flog2 ? (1u << flog2) / 32 : 0;
     t.root_word = filter_words;
     t.rank_word = filter_words + root_words;
-    t.lds_words = t.rank_word + rank_words;
+    t.short_word = t.rank_word + rank_words;
+    t.lds_words = t.short_word + (any_short ? root_words : 0);
     a->lds_image.assign(t.lds_words, 0);
     uint32_t *img = a->lds_image.data();
     uint32_t *root = img + t.root_word;
+    uint32_t *shrt = img + t.short_word;
     for (uint32_t j = 0; j < a->n_pats; j++) {
-        uint32_t key = root_key(P[j], D, bits);
+        const uint32_t key = root_key(P[j], D, bits);
         root[key >> 5] |= 1u << (key & 31);
+        if (any_short && a->pat_len[j] < K) shrt[key >> 5] |= 1u << (key & 31);
     }
     uint16_t *rank = reinterpret_cast<uint16_t *>(img + t.rank_word);
     uint32_t run = 0;
@@ -134,7 +163,8 @@ int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n
         a->max_len = maxl;
         a->nbw = (alphabet + 63) / 64;
         std::vector<const uint8_t *> P(pats, pats + n_pats);
-        std::vector<uint32_t> L(n_pats);
+        std::vector<uint32_t> &L = a->pat_len;
+        L.resize(n_pats);
         for (uint32_t j = 0; j < n_pats; j++) L[j] = (uint32_t)lens[j];
         // bytewise sort; a proper prefix sorts before its extensions; ties by id
         std::vector<uint32_t> ord(n_pats);

@@ -277,7 +277,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
     uint32_t mask = 0;
     if (!PACK2) {
         const uint32_t d[5] = {cur.x, cur.y, cur.z, cur.w, next_d0};
-        if (t.filter_k == 4) {
+        if (t.filter_k == 4 && !t.has_short) {
             const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
@@ -285,12 +285,20 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
                 mask |= probe(img, x, amask) << j;
             }
         } else if (t.filter_k) {
+            // k-gram filter, plus the short bitmap for patterns shorter than k
             const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
-            const uint32_t kmask = (1u << (8 * t.filter_k)) - 1u;
+            const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : (1u << (8 * t.filter_k)) - 1u;
+            const uint32_t *shrt = img + kLdsShort;
+            const bool two = t.root_depth == 2, sh = t.has_short;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
-                mask |= probe(img, x & kmask, amask) << j;
+                uint32_t p = probe(img, x & kmask, amask);
+                if (sh) {
+                    const uint32_t key = two ? (((x & 0xffu) << 8) | ((x >> 8) & 0xffu)) : (x & 0xffu);
+                    p |= probe_root(shrt, key);
+                }
+                mask |= p << j;
             }
         } else {
             // root image as the filter: D-byte key, first byte most significant
@@ -308,11 +316,17 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         const uint32_t K = t.filter_k ? t.filter_k : t.root_depth;
         const uint32_t rs = 32 - 2 * K;
         if (t.filter_k) {
+            // k-gram filter, plus the short bitmap (D-grams) for patterns shorter than k
             const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
+            const uint32_t *shrt = img + kLdsShort;
+            const uint32_t rsd = 32 - 2 * t.root_depth;
+            const bool sh = t.has_short;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
-                mask |= probe(img, rs >= 32 ? 0u : top >> rs, amask) << j;
+                uint32_t p = probe(img, rs >= 32 ? top : top >> rs, amask);
+                if (sh) p |= probe_root(shrt, top >> rsd);
+                mask |= p << j;
             }
         } else {
             const uint32_t *root = img + kLdsRoot;
@@ -508,10 +522,12 @@ __global__ __launch_bounds__(kThreads) void scan_count(DevTable t, const uint8_t
     __shared__ __align__(16) uint32_t img[kLdsWords];
     {
         // filter words to offset 0, root bitmap and rank table to their fixed places
-        const uint32_t fw = t.root_word, rw = t.rank_word - t.root_word, kw = t.lds_words - t.rank_word;
+        const uint32_t fw = t.root_word, rw = t.rank_word - t.root_word, kw = t.short_word - t.rank_word,
+                       sw = t.lds_words - t.short_word;
         for (uint32_t i = threadIdx.x; i < fw; i += kThreads) img[i] = t.lds_image[i];
-        for (uint32_t i = threadIdx.x; i < rw; i += kThreads) img[kLdsRoot + i] = t.lds_image[fw + i];
-        for (uint32_t i = threadIdx.x; i < kw; i += kThreads) img[kLdsRank + i] = t.lds_image[fw + rw + i];
+        for (uint32_t i = threadIdx.x; i < rw; i += kThreads) img[kLdsRoot + i] = t.lds_image[t.root_word + i];
+        for (uint32_t i = threadIdx.x; i < kw; i += kThreads) img[kLdsRank + i] = t.lds_image[t.rank_word + i];
+        for (uint32_t i = threadIdx.x; i < sw; i += kThreads) img[kLdsShort + i] = t.lds_image[t.short_word + i];
     }
     __syncthreads();  // the only barrier: waves run independently from here
 

@@ -36,6 +36,9 @@ constexpr uint32_t kMaxNodes = 0x7fffffffu;
 //   [filter: 2^filter_log2 bits]         k-gram prefix filter (optional), at offset 0
 //   [root bitmap: 2^root_bits bits]      D-gram -> present?   (D = root_depth)
 //   [root rank: 2^(root_bits-5) u16]     set bits before each 32-bit word
+//   [short bitmap: 2^root_bits bits]     D-grams of the patterns shorter than k (optional)
+// A start passes the prefilter when its k-gram is in the filter or its D-gram is in the
+// short bitmap; with no filter (k = D) it passes when its D-gram is in the root bitmap.
 // The root image folds the top D trie levels into one direct-indexed bitmap whose rank
 // (the popcount rule of Eq. 1 applied to a D-symbol root) is the breadth-first index of
 // the depth-D node: node = depth_start[D] + rank(key), keys in lexicographic order.
@@ -55,10 +58,12 @@ struct DevTable {
     uint32_t root_bits;         // D * bits-per-symbol
     uint32_t root_base;         // index of the first depth-D node
     uint32_t filter_k;          // k (symbols per filter key); 0 = no hashed filter
+    uint32_t has_short;         // 1: some pattern is shorter than k (short bitmap used)
     uint32_t filter_log2;       // log2(filter bits)
     uint32_t lds_words;         // total image size in 32-bit words
     uint32_t root_word;         // word offset of the root bitmap
     uint32_t rank_word;         // word offset of the rank table
+    uint32_t short_word;        // word offset of the short bitmap (= lds_words if none)
 };
 
 constexpr uint32_t kFilterMul = 0x9E3779B1u;  // multiplicative hash (golden ratio)
@@ -98,6 +103,7 @@ struct pfac_automaton {
     uint32_t nbw = 0;
     std::vector<uint32_t> depth_start;  // first node of each depth, depth 0..max_len+1
     std::vector<uint32_t> out_first, out_ids;
+    std::vector<uint32_t> pat_len;
     // Device images.
     std::vector<uint64_t> dev_nodes, dev_bm;
     std::vector<uint32_t> lds_image;

@@ -29,7 +29,8 @@ constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bit
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
 constexpr uint32_t kLdsRoot = kFilterWordsMax;
 constexpr uint32_t kLdsRank = kLdsRoot + kRootWordsMax;
-constexpr uint32_t kLdsQueues = kLdsRank + kRankWordsMax;
+constexpr uint32_t kLdsShort = kLdsRank + kRankWordsMax;
+constexpr uint32_t kLdsQueues = kLdsShort + kRootWordsMax;
 constexpr uint32_t kLdsWords = kLdsQueues + kWaves * kWaveLds / 4;
 constexpr uint32_t kMaxFilterLog2 = 19;
 
