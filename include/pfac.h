@@ -145,6 +145,56 @@ PFAC_API int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t 
 PFAC_API int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
                        uint64_t cap, uint64_t *h_count, void *stream);
 
+/* ------------------------------------------------------------------- packet batches
+ * pfac_scan_batch_async -- scan a batch of packets held back to back in device memory
+ * (CSR): packet i is d_bytes[d_offsets[i] .. d_offsets[i+1]), with d_offsets[0] = 0,
+ * non-decreasing, d_offsets[n_pkts] = n_bytes (device memory, n_pkts + 1 entries; empty
+ * packets are allowed). Each packet is its own text in the sense of Section 2.2: a walk
+ * stops at its packet's end, so no match crosses a packet boundary. Keys use the global
+ * byte offset as the start, so key order is (packet, start in packet, pattern id); map a
+ * start back to its packet by an upper bound over the offsets. Offsets that break the
+ * rules above give unspecified matches but no access outside d_bytes[0 .. n_bytes).
+ * All packets go through one pair of persistent launches (count, then placement), not
+ * one launch per packet. Count, capacity, scratch and errors as pfac_scan_async; the
+ * automaton's PFAC_ALGO_PLAIN choice does not apply to batches. n_pkts == 0 gives 0. */
+PFAC_API int pfac_scan_batch_async(pfac_automaton *a, const uint8_t *d_bytes, const uint64_t *d_offsets,
+                                   uint32_t n_pkts, uint64_t n_bytes, uint64_t *d_keys, uint64_t cap,
+                                   uint64_t *d_count, void *stream);
+
+/* pfac_scan_batch -- pfac_scan_batch_async, then wait and return the count in *h_count,
+ * with PFAC_ECAPACITY as in pfac_scan. */
+PFAC_API int pfac_scan_batch(pfac_automaton *a, const uint8_t *d_bytes, const uint64_t *d_offsets,
+                             uint32_t n_pkts, uint64_t n_bytes, uint64_t *d_keys, uint64_t cap,
+                             uint64_t *h_count, void *stream);
+
+/* ------------------------------------------------------------------- captured graphs
+ * pfac_graph_create -- record one scan (a text when d_offsets is NULL, else a packet
+ * batch) into a HIP graph that is replayed with pfac_graph_launch. The buffers are fixed
+ * at creation; the sizes of each replay are read at run time from d_sizes (device memory,
+ * two uint64: bytes, packets), bounded by max_bytes / max_pkts, so one graph serves
+ * every batch up to those bounds: the caller writes new bytes, offsets and sizes into
+ * the same buffers (stream-ordered) and launches again. d_offsets, when given, holds
+ * max_pkts + 1 entries. The graph owns its scratch (allocated here, before capture),
+ * uses no memset nodes, and resets its own device counters at the end of every replay.
+ * `stream` is used for the capture and must not be the NULL stream. Keys, count and
+ * capacity as pfac_scan_async. Errors: PFAC_EINVAL (NULL pointers, max_bytes == 0,
+ * max_pkts == 0 with offsets, automaton without patterns), PFAC_ETOO_LARGE
+ * (max_bytes >= 2^32), PFAC_ENODEVICE, PFAC_ENOMEM, PFAC_EHIP (capture failed). On
+ * error *out is NULL. Free with pfac_graph_destroy after the last replay completed. */
+typedef struct pfac_graph pfac_graph;
+
+PFAC_API int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, const uint64_t *d_offsets,
+                               uint64_t max_bytes, uint32_t max_pkts, uint64_t *d_keys, uint64_t cap,
+                               uint64_t *d_count, const uint64_t *d_sizes, void *stream, pfac_graph **out);
+
+/* Replay the graph on `stream` (any stream of the graph's device). Replays of one graph
+ * share its scratch, so they must not run concurrently (keep them on one stream).
+ * Errors: PFAC_EINVAL, PFAC_EHIP. */
+PFAC_API int pfac_graph_launch(pfac_graph *g, void *stream);
+
+/* Free the graph and its scratch. NULL is a no-op. */
+PFAC_API void pfac_graph_destroy(pfac_graph *g);
+
 /* ------------------------------------------------------------------- tuning
  * Launch choices of an automaton's scans. None of them changes any result.
  *   algo  PFAC_ALGO_AUTO (= TILED), PFAC_ALGO_PLAIN (one lane per start, trie walked

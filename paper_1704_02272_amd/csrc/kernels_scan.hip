@@ -363,7 +363,9 @@ struct Scanner {
     bool aligned;
 
     __device__ __forceinline__ uint64_t end_of(uint64_t s) const {
-        return SEG ? packet_end(offsets, n_packets, s) : n;
+        if (!SEG) return n;
+        const uint64_t e = packet_end(offsets, n_packets, s);
+        return e < n ? e : n;
     }
 
     // Walk `cnt` queued survivors from q[first], one per lane; record the matching ones.
@@ -518,8 +520,13 @@ struct Scanner {
 template <int LAYOUT, bool PACK2, bool SEG>
 __global__ __launch_bounds__(kThreads) void scan_count(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
                                                       const uint64_t *__restrict__ offsets, uint32_t n_packets,
-                                                      SpanOut so, uint32_t n_spans) {
+                                                      SpanOut so, const uint64_t *__restrict__ sizes) {
     __shared__ __align__(16) uint32_t img[kLdsWords];
+    if (sizes) {  // sizes of this batch, bounded by those the launch was set up for
+        n = sizes[0] < n ? sizes[0] : n;
+        n_packets = sizes[1] < n_packets ? (uint32_t)sizes[1] : n_packets;
+    }
+    const uint32_t n_spans = (uint32_t)((n + kSpan - 1) / kSpan);
     {
         // filter words to offset 0, root bitmap and rank table to their fixed places
         const uint32_t fw = t.root_word, rw = t.rank_word - t.root_word, kw = t.short_word - t.rank_word,
@@ -550,82 +557,99 @@ __global__ __launch_bounds__(kThreads) void scan_count(DevTable t, const uint8_t
 }
 
 // ------------------------------------------------------------------ placement kernel
+// Persistent: each workgroup takes block tickets until they run out, and finishes one
+// block (sum, look-back, keys) before it takes the next, so a look-back only ever waits
+// on blocks that running workgroups are working on.
 template <int LAYOUT, bool SEG>
 __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
                                                            const uint64_t *__restrict__ offsets, uint32_t n_packets,
                                                            uint64_t *__restrict__ keys, uint64_t cap,
                                                            uint64_t *__restrict__ d_count, SpanOut so, TileState ts,
-                                                           uint32_t n_spans, uint32_t n_blocks) {
+                                                           const uint64_t *__restrict__ sizes) {
     __shared__ uint64_t span_off[kBlockSpans];
     __shared__ uint32_t sh[4];
+    if (sizes) {
+        n = sizes[0] < n ? sizes[0] : n;
+        n_packets = sizes[1] < n_packets ? (uint32_t)sizes[1] : n_packets;
+    }
+    const uint32_t n_spans = (uint32_t)((n + kSpan - 1) / kSpan);
+    const uint32_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const Trie<LAYOUT> T{t};
-    if (threadIdx.x == 0) {
-        sh[0] = __hip_atomic_fetch_add(&ts.ctrl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sh[1] = __hip_atomic_load(&ts.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) sh[1] = __hip_atomic_load(&ts.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const uint32_t blk = sh[0], epoch = sh[1];
+    const uint32_t epoch = sh[1];
     const uint64_t tagE = (uint64_t)epoch << 44;
-    if (blk < n_blocks && wave == 0) {
-        // the block's span counts, their prefix, and the block's place by look-back
-        const uint32_t sp = blk * kBlockSpans + lane;
-        const uint64_t c = sp < n_spans ? so.cnt[sp] : 0;
-        uint64_t inc = c;
+    auto end_of = [&](uint64_t s) -> uint64_t {
+        if (!SEG) return n;
+        const uint64_t e = packet_end(offsets, n_packets, s);
+        return e < n ? e : n;
+    };
+    for (;;) {
+        if (threadIdx.x == 0) sh[0] = __hip_atomic_fetch_add(&ts.ctrl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t blk = sh[0];
+        __syncthreads();  // sh[0] is rewritten by the next take
+        if (blk >= n_blocks) break;
+        if (wave == 0) {
+            // the block's span counts, their prefix, and the block's place by look-back
+            const uint32_t sp = blk * kBlockSpans + lane;
+            const uint64_t c = sp < n_spans ? so.cnt[sp] : 0;
+            uint64_t inc = c;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint64_t u = __shfl_up(inc, d, 64);
-            if (lane >= (uint32_t)d) inc += u;
-        }
-        const uint64_t total = __shfl(inc, 63, 64);
-        if (lane == 0) {
-            const uint64_t v = total > kValueMask ? kValueMask : total;
-            __hip_atomic_store(&ts.word[blk], tagE | ((blk == 0 ? kFlagInc : kFlagAgg) << 42) | v,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        uint64_t excl = 0;
-        if (blk > 0) {
-            int64_t j = (int64_t)blk - 1;
-            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-            for (;;) {
-                const int64_t idx = j - (int64_t)lane;
-                uint64_t wd = tagE | (kFlagInc << 42);  // before block 0: prefix 0
-                if (idx >= 0) wd = __hip_atomic_load(&ts.word[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t flag = (uint32_t)(wd >> 42) & 3u;
-                const bool ready = (wd >> 44) == epoch && flag != 0;
-                const bool isinc = ready && flag == kFlagInc;
-                const uint64_t incm = __ballot(isinc);
-                const uint32_t first = incm ? (uint32_t)__builtin_ctzll(incm) : 64u;
-                const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
-                if (__ballot(!ready) & need) {
-                    if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {  // never expected
-                        if (lane == 0) {
-                            __hip_atomic_fetch_or(&ts.ctrl[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                        }
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += wave_sum64(lane <= first ? (wd & kValueMask) : 0);
-                if (first < 64) break;
-                j -= 64;
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint64_t u = __shfl_up(inc, d, 64);
+                if (lane >= (uint32_t)d) inc += u;
             }
+            const uint64_t total = __shfl(inc, 63, 64);
             if (lane == 0) {
-                uint64_t v = excl + total;
-                if (v > kValueMask) {
-                    __hip_atomic_fetch_or(&ts.ctrl[3], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    v = kValueMask;
-                }
-                __hip_atomic_store(&ts.word[blk], tagE | (kFlagInc << 42) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t v = total > kValueMask ? kValueMask : total;
+                __hip_atomic_store(&ts.word[blk], tagE | ((blk == 0 ? kFlagInc : kFlagAgg) << 42) | v,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            uint64_t excl = 0;
+            if (blk > 0) {
+                int64_t j = (int64_t)blk - 1;
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                for (;;) {
+                    const int64_t idx = j - (int64_t)lane;
+                    uint64_t wd = tagE | (kFlagInc << 42);  // before block 0: prefix 0
+                    if (idx >= 0) wd = __hip_atomic_load(&ts.word[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t flag = (uint32_t)(wd >> 42) & 3u;
+                    const bool ready = (wd >> 44) == epoch && flag != 0;
+                    const bool isinc = ready && flag == kFlagInc;
+                    const uint64_t incm = __ballot(isinc);
+                    const uint32_t first = incm ? (uint32_t)__builtin_ctzll(incm) : 64u;
+                    const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+                    if (__ballot(!ready) & need) {
+                        if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {  // never expected
+                            if (lane == 0) {
+                                __hip_atomic_fetch_or(&ts.ctrl[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                            }
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    excl += wave_sum64(lane <= first ? (wd & kValueMask) : 0);
+                    if (first < 64) break;
+                    j -= 64;
+                }
+                if (lane == 0) {
+                    uint64_t v = excl + total;
+                    if (v > kValueMask) {
+                        __hip_atomic_fetch_or(&ts.ctrl[3], 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                        v = kValueMask;
+                    }
+                    __hip_atomic_store(&ts.word[blk], tagE | (kFlagInc << 42) | v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            span_off[lane] = excl + inc - c;
         }
-        span_off[lane] = excl + inc - c;
-    }
-    __syncthreads();
-    if (blk < n_blocks) {
+        __syncthreads();
         // each wave writes the keys of every kPlaceWaves-th span of the block
         for (uint32_t i = wave; i < kBlockSpans; i += kPlaceWaves) {
             const uint32_t sp = blk * kBlockSpans + i;
@@ -636,10 +660,10 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             const uint32_t nh = so.nh[sp], ovf = so.ovf[sp];
             for (uint32_t h0 = 0; h0 < nh; h0 += 64) {
                 const bool on = h0 + lane < nh;
-                uint64_t rec = on ? so.rec[(size_t)sp * kHCap + h0 + lane] : 0;
+                const uint64_t rec = on ? so.rec[(size_t)sp * kHCap + h0 + lane] : 0;
                 const uint64_t s = a + (rec & 0xffffu);
                 const uint32_t nterm = (uint32_t)(rec >> 16) & 0xffffu, q0 = (uint32_t)(rec >> 32);
-                const uint64_t end = on ? (SEG ? packet_end(offsets, n_packets, s) : n) : 0;
+                const uint64_t end = on ? end_of(s) : 0;
                 uint32_t c = 0;
                 if (on) c = nterm == 1 ? T.ids(q0) : T.walk_from(0, text, s, end).cnt;
                 const uint32_t incl = wave_incl_scan(c);
@@ -663,7 +687,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                 for (uint64_t s0 = a + ovf; s0 < top; s0 += 64) {
                     const uint64_t s = s0 + lane;
                     const bool on = s < top;
-                    const uint64_t end = on ? (SEG ? packet_end(offsets, n_packets, s) : n) : 0;
+                    const uint64_t end = on ? end_of(s) : 0;
                     const uint32_t c = on ? T.walk_from(0, text, s, end).cnt : 0;
                     const uint32_t incl = wave_incl_scan(c);
                     const uint64_t o = run + incl - c;
@@ -672,9 +696,9 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                 }
             }
         }
+        __syncthreads();  // span_off is rewritten by the next block
     }
     // last workgroup out: writes the count, resets the ticket, advances the epoch
-    __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t done = __hip_atomic_fetch_add(&ts.ctrl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (done == gridDim.x - 1) {
@@ -713,32 +737,34 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
 template <int LAYOUT, bool PACK2, bool SEG>
 int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-               uint32_t grid, hipStream_t s) {
-    const uint32_t n_spans = (uint32_t)((n + kSpan - 1) / kSpan);
-    const uint32_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
-    auto k = scan_count<LAYOUT, PACK2, SEG>;
+               const uint64_t *sizes, uint32_t grid, hipStream_t s) {
+    const uint64_t n_spans = (n + kSpan - 1) / kSpan;
+    const uint64_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
+    auto kc = scan_count<LAYOUT, PACK2, SEG>;
+    auto kp = place_emit<LAYOUT, SEG>;
     static std::once_flag once;
-    static int cus = 0;
-    static int per_cu = 1;
+    static int cus = 0, per_cu = 1, per_cu_p = 1;
     std::call_once(once, [&] {
         int dev = 0;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (cus <= 0) cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, 0) != hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kc, kThreads, 0) != hipSuccess || per_cu < 1)
             per_cu = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_p, kp, kPlaceThreads, 0) != hipSuccess || per_cu_p < 1)
+            per_cu_p = 1;
     });
-    if (grid == 0) {
-        // as many workgroups as are resident at once, no more than it takes to give
-        // every wave a span
-        const uint64_t g = (uint64_t)cus * (uint32_t)per_cu;
-        const uint64_t need = (n_spans + kWaves - 1) / kWaves;
-        grid = (uint32_t)(g < need ? g : need);
-        if (grid == 0) grid = 1;
-    }
-    k<<<grid, kThreads, 0, s>>>(t, text, n, offsets, n_packets, so, n_spans);
-    place_emit<LAYOUT, SEG><<<n_blocks, kPlaceThreads, 0, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count,
-                                                                so, ts, n_spans, n_blocks);
+    // count: as many workgroups as are resident at once, no more than it takes to give
+    // every wave a span (n is the upper bound when sizes come from device memory)
+    uint64_t gc = grid ? grid : (uint64_t)cus * (uint32_t)per_cu;
+    const uint64_t need = (n_spans + kWaves - 1) / kWaves;
+    if (gc > need) gc = need;
+    if (gc == 0) gc = 1;
+    uint64_t gp = (uint64_t)cus * (uint32_t)per_cu_p;
+    if (gp > n_blocks) gp = n_blocks;
+    if (gp == 0) gp = 1;
+    kc<<<(uint32_t)gc, kThreads, 0, s>>>(t, text, n, offsets, n_packets, so, sizes);
+    kp<<<(uint32_t)gp, kPlaceThreads, 0, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -746,11 +772,12 @@ int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_
 
 int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                  uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-                 uint32_t grid, hipStream_t s) {
+                 const uint64_t *sizes, uint32_t grid, hipStream_t s) {
     const bool seg = offsets != nullptr;
     const bool narrow = t.layout == LAYOUT_NARROW;
     const bool pack2 = t.pack2 != 0;
-#define PFAC_L(LA, P2, SG) return launch_one<LA, P2, SG>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, grid, s)
+#define PFAC_L(LA, P2, SG) \
+    return launch_one<LA, P2, SG>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, s)
     if (narrow) {
         if (pack2) { if (seg) PFAC_L(LAYOUT_NARROW, true, true); else PFAC_L(LAYOUT_NARROW, true, false); }
         else { if (seg) PFAC_L(LAYOUT_NARROW, false, true); else PFAC_L(LAYOUT_NARROW, false, false); }

@@ -143,6 +143,8 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     return PFAC_OK;
 }
 
+static int ensure_tiles(Workspace *w, uint64_t n, void *stream);
+
 static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo, Workspace **out) {
     Workspace *&w = c->workspaces[stream];
     if (!w) {
@@ -154,29 +156,8 @@ static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo,
             return PFAC_ENOMEM;
     }
     if (algo == PFAC_ALGO_TILED) {
-        const uint64_t ns = (n + kSpan - 1) / kSpan;
-        if (ns > w->cap_spans || !w->ts.ctrl) {
-            if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
-            free_tiles(w);
-            const uint64_t spans = ns < 1024 ? 1024 : ns + ns / 4;
-            const uint64_t blocks = (spans + kBlockSpans - 1) / kBlockSpans;
-            if (hipMalloc(&w->so.cnt, spans * 8) != hipSuccess) return PFAC_ENOMEM;
-            if (hipMalloc(&w->so.nh, spans * 4) != hipSuccess) return PFAC_ENOMEM;
-            if (hipMalloc(&w->so.ovf, spans * 4) != hipSuccess) return PFAC_ENOMEM;
-            if (hipMalloc(&w->so.rec, spans * kHCap * 8) != hipSuccess) return PFAC_ENOMEM;
-            if (hipMalloc(&w->ts.word, blocks * 8) != hipSuccess) return PFAC_ENOMEM;
-            if (hipMalloc(&w->ts.ctrl, 16) != hipSuccess) return PFAC_ENOMEM;
-            w->cap_spans = spans;
-            w->cap_tiles = blocks;
-            w->launches = kEpochPeriod;  // forces a clear before the first launch
-        }
-        if (w->launches >= kEpochPeriod) {
-            // words 0 never match an epoch (epochs start at 1); clearing before the
-            // device epoch can wrap keeps stale words from ever matching
-            clear_tiles_kernel<<<256, 256, 0, (hipStream_t)stream>>>(w->ts.word, w->cap_tiles, w->ts.ctrl);
-            if (hipGetLastError() != hipSuccess) return PFAC_EHIP;
-            w->launches = 0;
-        }
+        const int rc = ensure_tiles(w, n, stream);
+        if (rc) return rc;
         *out = w;
         return PFAC_OK;
     }
@@ -219,8 +200,43 @@ extern "C" int pfac_upload(pfac_automaton *a, int device) {
     return rc;
 }
 
-static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
-                        uint64_t cap, uint64_t *d_count, void *stream, Workspace **ws_out) {
+namespace pfac {
+
+// Tiled-path scratch for n bytes in workspace w (grown on demand; the stream is drained
+// before old buffers are freed). Clears the look-back words before the epoch could wrap.
+static int ensure_tiles(Workspace *w, uint64_t n, void *stream) {
+    const uint64_t ns = (n + kSpan - 1) / kSpan;
+    if (ns > w->cap_spans || !w->ts.ctrl) {
+        if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
+        free_tiles(w);
+        const uint64_t spans = ns < 1024 ? 1024 : ns + ns / 4;
+        const uint64_t blocks = (spans + kBlockSpans - 1) / kBlockSpans;
+        if (hipMalloc(&w->so.cnt, spans * 8) != hipSuccess) return PFAC_ENOMEM;
+        if (hipMalloc(&w->so.nh, spans * 4) != hipSuccess) return PFAC_ENOMEM;
+        if (hipMalloc(&w->so.ovf, spans * 4) != hipSuccess) return PFAC_ENOMEM;
+        if (hipMalloc(&w->so.rec, spans * kHCap * 8) != hipSuccess) return PFAC_ENOMEM;
+        if (hipMalloc(&w->ts.word, blocks * 8) != hipSuccess) return PFAC_ENOMEM;
+        if (hipMalloc(&w->ts.ctrl, 16) != hipSuccess) return PFAC_ENOMEM;
+        w->cap_spans = spans;
+        w->cap_tiles = blocks;
+        w->launches = kEpochPeriod;  // forces a clear before the first launch
+    }
+    if (w->launches >= kEpochPeriod) {
+        // words 0 never match an epoch (epochs start at 1); clearing before the device
+        // epoch can wrap keeps stale words from ever matching
+        clear_tiles_kernel<<<256, 256, 0, (hipStream_t)stream>>>(w->ts.word, w->cap_tiles, w->ts.ctrl);
+        if (hipGetLastError() != hipSuccess) return PFAC_EHIP;
+        w->launches = 0;
+    }
+    return PFAC_OK;
+}
+
+}  // namespace pfac
+
+// Enqueue one scan of a text (offsets == null) or a packet batch.
+static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, const uint64_t *d_offsets,
+                        uint32_t n_pkts, uint64_t *d_keys, uint64_t cap, uint64_t *d_count, void *stream,
+                        Workspace **ws_out) {
     if (!a) return PFAC_EINVAL;
     if (n > 0 && !d_text) return PFAC_EINVAL;
     if (cap > 0 && !d_keys) return PFAC_EINVAL;
@@ -230,13 +246,14 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, ui
     DeviceCopy *c = nullptr;
     int rc = get_copy(a, &c);
     if (rc) return rc;
-    const uint32_t algo = a->algo == PFAC_ALGO_PLAIN ? PFAC_ALGO_PLAIN : PFAC_ALGO_TILED;
+    const bool batch = d_offsets != nullptr;
+    const uint32_t algo = (a->algo == PFAC_ALGO_PLAIN && !batch) ? PFAC_ALGO_PLAIN : PFAC_ALGO_TILED;
     Workspace *w = nullptr;
     rc = get_workspace(c, stream, n, algo, &w);
     if (rc) return rc;
     if (ws_out) *ws_out = w;
     uint64_t *cnt = d_count ? d_count : w->d_count;
-    if (n == 0 || a->n_pats == 0) return launch_set_u64(cnt, 0, s) ? PFAC_EHIP : PFAC_OK;
+    if (n == 0 || a->n_pats == 0 || (batch && n_pkts == 0)) return launch_set_u64(cnt, 0, s) ? PFAC_EHIP : PFAC_OK;
     if (algo == PFAC_ALGO_PLAIN) {
         if (launch_plain(c->view, d_text, n, d_keys, cap, cnt, w->block_counts, w->block_offsets, s))
             return PFAC_EHIP;
@@ -244,24 +261,13 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, ui
     }
     const uint64_t ns = (n + kSpan - 1) / kSpan;
     const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, (ns + kWaves - 1) / kWaves) : 0u;
-    if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, cnt, w->so, w->ts, grid, s))
+    if (launch_tiled(c->view, d_text, n, d_offsets, n_pkts, d_keys, cap, cnt, w->so, w->ts, nullptr, grid, s))
         return PFAC_EHIP;
     w->launches++;
     return PFAC_OK;
 }
 
-extern "C" int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t n,
-                               uint64_t *d_keys, uint64_t cap, uint64_t *d_count, void *stream) {
-    if (!d_count) return PFAC_EINVAL;
-    return scan_enqueue(a, d_text, n, d_keys, cap, d_count, stream, nullptr);
-}
-
-extern "C" int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
-                         uint64_t cap, uint64_t *h_count, void *stream) {
-    if (!h_count) return PFAC_EINVAL;
-    Workspace *w = nullptr;
-    int rc = scan_enqueue(a, d_text, n, d_keys, cap, nullptr, stream, &w);
-    if (rc) return rc;
+static int finish_count(Workspace *w, uint64_t cap, uint64_t *h_count, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(w->h_count, w->d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return PFAC_EHIP;
@@ -271,6 +277,123 @@ extern "C" int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, u
     if (*h_count == kCountOverflow) return PFAC_ETOO_LARGE;
     return *h_count > cap ? PFAC_ECAPACITY : PFAC_OK;
 }
+
+extern "C" int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t n,
+                               uint64_t *d_keys, uint64_t cap, uint64_t *d_count, void *stream) {
+    if (!d_count) return PFAC_EINVAL;
+    return scan_enqueue(a, d_text, n, nullptr, 0, d_keys, cap, d_count, stream, nullptr);
+}
+
+extern "C" int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
+                         uint64_t cap, uint64_t *h_count, void *stream) {
+    if (!h_count) return PFAC_EINVAL;
+    Workspace *w = nullptr;
+    int rc = scan_enqueue(a, d_text, n, nullptr, 0, d_keys, cap, nullptr, stream, &w);
+    if (rc) return rc;
+    return finish_count(w, cap, h_count, stream);
+}
+
+extern "C" int pfac_scan_batch_async(pfac_automaton *a, const uint8_t *d_bytes, const uint64_t *d_offsets,
+                                     uint32_t n_pkts, uint64_t n_bytes, uint64_t *d_keys, uint64_t cap,
+                                     uint64_t *d_count, void *stream) {
+    if (!d_count || (!d_offsets && n_pkts > 0)) return PFAC_EINVAL;
+    if (n_pkts == 0) return scan_enqueue(a, d_bytes, 0, nullptr, 0, d_keys, cap, d_count, stream, nullptr);
+    return scan_enqueue(a, d_bytes, n_bytes, d_offsets, n_pkts, d_keys, cap, d_count, stream, nullptr);
+}
+
+extern "C" int pfac_scan_batch(pfac_automaton *a, const uint8_t *d_bytes, const uint64_t *d_offsets,
+                               uint32_t n_pkts, uint64_t n_bytes, uint64_t *d_keys, uint64_t cap,
+                               uint64_t *h_count, void *stream) {
+    if (!h_count || (!d_offsets && n_pkts > 0)) return PFAC_EINVAL;
+    Workspace *w = nullptr;
+    int rc = n_pkts == 0 ? scan_enqueue(a, d_bytes, 0, nullptr, 0, d_keys, cap, nullptr, stream, &w)
+                         : scan_enqueue(a, d_bytes, n_bytes, d_offsets, n_pkts, d_keys, cap, nullptr, stream, &w);
+    if (rc) return rc;
+    return finish_count(w, cap, h_count, stream);
+}
+
+// ------------------------------------------------------------------ captured graphs
+struct pfac_graph {
+    pfac_automaton *a = nullptr;
+    int device = -1;
+    Workspace ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void graph_free(pfac_graph *g) {
+    if (!g) return;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (g->device >= 0) (void)hipSetDevice(g->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    free_tiles(&g->ws);
+    (void)hipSetDevice(prev);
+    delete g;
+}
+
+extern "C" int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, const uint64_t *d_offsets,
+                                 uint64_t max_bytes, uint32_t max_pkts, uint64_t *d_keys, uint64_t cap,
+                                 uint64_t *d_count, const uint64_t *d_sizes, void *stream, pfac_graph **out) {
+    if (!out) return PFAC_EINVAL;
+    *out = nullptr;
+    if (!a || !stream || !d_bytes || !d_count || !d_sizes || max_bytes == 0 || (cap > 0 && !d_keys))
+        return PFAC_EINVAL;
+    if (d_offsets && max_pkts == 0) return PFAC_EINVAL;
+    if (max_bytes >= (1ull << 32)) return PFAC_ETOO_LARGE;
+    if (a->n_pats == 0) return PFAC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    pfac_graph *g = new (std::nothrow) pfac_graph();
+    if (!g) return PFAC_ENOMEM;
+    g->a = a;
+    DevTable view{};
+    {
+        std::lock_guard<std::mutex> lk(a->mu);
+        DeviceCopy *c = nullptr;
+        int rc = get_copy(a, &c);
+        if (rc) {
+            delete g;
+            return rc;
+        }
+        g->device = c->device;
+        view = c->view;
+    }
+    // everything that allocates happens before the capture
+    int rc = ensure_tiles(&g->ws, max_bytes, stream);
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = PFAC_EHIP;
+    if (!rc && hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = PFAC_EHIP;
+    if (!rc) {
+        const int lr = launch_tiled(view, d_bytes, max_bytes, d_offsets, d_offsets ? max_pkts : 0, d_keys, cap,
+                                    d_count, g->ws.so, g->ws.ts, d_sizes, a->grid, s);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        g->graph = graph;
+        if (lr || ec != hipSuccess || !graph) rc = PFAC_EHIP;
+    }
+    if (!rc && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) rc = PFAC_EHIP;
+    if (rc) {
+        graph_free(g);
+        return rc;
+    }
+    *out = g;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_graph_launch(pfac_graph *g, void *stream) {
+    if (!g || !g->exec) return PFAC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (g->ws.launches >= kEpochPeriod) {
+        clear_tiles_kernel<<<256, 256, 0, s>>>(g->ws.ts.word, g->ws.cap_tiles, g->ws.ts.ctrl);
+        if (hipGetLastError() != hipSuccess) return PFAC_EHIP;
+        g->ws.launches = 0;
+    }
+    if (hipGraphLaunch(g->exec, s) != hipSuccess) return PFAC_EHIP;
+    g->ws.launches++;
+    return PFAC_OK;
+}
+
+extern "C" void pfac_graph_destroy(pfac_graph *g) { graph_free(g); }
 
 extern "C" int pfac_set_tuning(pfac_automaton *a, const pfac_tuning *t) {
     if (!a || !t) return PFAC_EINVAL;

@@ -69,10 +69,12 @@ struct TileState {
 constexpr uint64_t kCountTimeout = ~0ull;
 constexpr uint64_t kCountOverflow = ~0ull - 1;
 
-// Count kernel then placement kernel on stream s. grid: workgroups of the count kernel
-// (0 = as many as are resident at once).
+// Count kernel then placement kernel on stream s. offsets: packet offsets (n_packets + 1)
+// or null for one text. sizes: null, or device {n, n_packets} read at run time and
+// bounded by the n / n_packets given here (graph replays). grid: workgroups of the
+// count kernel (0 = as many as are resident at once).
 int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                  uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-                 uint32_t grid, hipStream_t s);
+                 const uint64_t *sizes, uint32_t grid, hipStream_t s);
 
 }  // namespace pfac

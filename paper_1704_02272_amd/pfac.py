@@ -78,6 +78,14 @@ def lib():
             "pfac_upload": (C.c_int, [VP, C.c_int]),
             "pfac_scan_async": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
             "pfac_scan": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, P64, VP]),
+            "pfac_scan_batch_async": (C.c_int, [VP, VP, VP, C.c_uint32, C.c_uint64, VP, C.c_uint64,
+                                                VP, VP]),
+            "pfac_scan_batch": (C.c_int, [VP, VP, VP, C.c_uint32, C.c_uint64, VP, C.c_uint64,
+                                          P64, VP]),
+            "pfac_graph_create": (C.c_int, [VP, VP, VP, C.c_uint64, C.c_uint32, VP, C.c_uint64,
+                                            VP, VP, VP, C.POINTER(VP)]),
+            "pfac_graph_launch": (C.c_int, [VP, VP]),
+            "pfac_graph_destroy": (None, [VP]),
             "pfac_set_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
             "pfac_get_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
         }
@@ -229,6 +237,100 @@ def pfac_scan(a: Automaton, text, keys=None, stream=None):
         _check(rc, "pfac_scan")
         return keys[:int(cnt.value)]
     raise PfacError(PFAC_ECAPACITY, "pfac_scan")
+
+
+def _device_u64(t, what):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int64 and t.is_contiguous()):
+        raise TypeError("%s must be a contiguous int64 tensor on a ROCm device" % what)
+    return t
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+
+def pfac_scan_batch_async(a: Automaton, data, offsets, keys, count, stream=None):
+    """Enqueue a scan of a packet batch: ``data`` uint8 device tensor holding the packets
+    back to back, ``offsets`` int64 device tensor of n_pkts + 1 packet offsets."""
+    data = _device_u8(data)
+    offsets = _device_u64(offsets, "offsets")
+    rc = lib().pfac_scan_batch_async(a.handle, _ptr(data), _ptr(offsets), max(offsets.numel() - 1, 0),
+                                     data.numel(), _ptr(keys), keys.numel(), _ptr(count),
+                                     _stream_handle(stream))
+    _check(rc, "pfac_scan_batch_async")
+
+
+def pfac_scan_batch(a: Automaton, data, offsets, keys=None, stream=None):
+    """Blocking packet-batch scan; returns the sorted keys (global byte offset << 32 | id)
+    as an int64 device tensor, growing ``keys`` on PFAC_ECAPACITY as pfac_scan does."""
+    import torch
+    data = _device_u8(data)
+    offsets = _device_u64(offsets, "offsets")
+    if keys is None:
+        keys = torch.empty(max(1024, data.numel() // 256), dtype=torch.int64, device=data.device)
+    cnt = C.c_uint64(0)
+    for _ in range(2):
+        rc = lib().pfac_scan_batch(a.handle, _ptr(data), _ptr(offsets), max(offsets.numel() - 1, 0),
+                                   data.numel(), _ptr(keys), keys.numel(), C.byref(cnt),
+                                   _stream_handle(stream))
+        if rc == PFAC_ECAPACITY:
+            keys = torch.empty(int(cnt.value), dtype=torch.int64, device=data.device)
+            continue
+        _check(rc, "pfac_scan_batch")
+        return keys[:int(cnt.value)]
+    raise PfacError(PFAC_ECAPACITY, "pfac_scan_batch")
+
+
+class Graph:
+    """Owns a ``pfac_graph*`` (a captured scan, replayed with :meth:`launch`). Keeps the
+    tensors it was recorded on alive."""
+
+    def __init__(self, handle, tensors):
+        self.handle = handle
+        self._tensors = tensors
+
+    def launch(self, stream=None):
+        _check(lib().pfac_graph_launch(self.handle, _stream_handle(stream)), "pfac_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().pfac_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pfac_graph_create(a: Automaton, data, offsets, keys, count, sizes, stream) -> Graph:
+    """Record a scan of ``data`` (uint8 device tensor; its numel is the byte bound) as a
+    packet batch over ``offsets`` (int64 device tensor, max packets + 1; None for one
+    text) into a HIP graph. ``sizes``: int64 device tensor {bytes, packets} read at each
+    replay. ``stream`` must be a non-default torch stream."""
+    data = _device_u8(data)
+    if offsets is not None:
+        offsets = _device_u64(offsets, "offsets")
+    sizes = _device_u64(sizes, "sizes")
+    h = C.c_void_p()
+    n_pk = offsets.numel() - 1 if offsets is not None else 0
+    rc = lib().pfac_graph_create(a.handle, _ptr(data), _ptr(offsets), data.numel(), n_pk, _ptr(keys),
+                                 keys.numel(), _ptr(count), _ptr(sizes), _stream_handle(stream), C.byref(h))
+    _check(rc, "pfac_graph_create")
+    return Graph(h.value, (data, offsets, keys, count, sizes, a))
+
+
+def key_to_packet(keys: np.ndarray, offsets: np.ndarray):
+    """Host helper: (packet index, start within packet, pattern id) of uint64 keys from a
+    batch scan, by an upper bound of each start over the packet offsets."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    starts = (keys >> np.uint64(32)).astype(np.int64)
+    ids = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    offs = np.asarray(offsets, dtype=np.int64)
+    pk = np.searchsorted(offs, starts, side="right") - 1
+    return pk, starts - offs[pk], ids
 
 
 def keys_to_numpy(keys) -> np.ndarray:

@@ -113,3 +113,29 @@ def test_empty_pattern_set():
     a = pfac.pfac_build([], 256)
     info = pfac.pfac_table_info(a)
     assert info["n_nodes"] == 1 and info["n_patterns"] == 0
+
+
+def test_key_to_packet_host_helper():
+    # packets "a" | "bc" | "" | "ab" at offsets 0, 1, 3, 3; keys (start << 32) | id
+    offsets = np.array([0, 1, 3, 3, 5], dtype=np.uint64)
+    keys = np.array([(1 << 32) | 2, (3 << 32) | 0, (4 << 32) | 7], dtype=np.uint64)
+    pk, off, ids = pfac.key_to_packet(keys, offsets)
+    assert pk.tolist() == [1, 3, 3]      # an empty packet never owns a start
+    assert off.tolist() == [0, 0, 1]
+    assert ids.tolist() == [2, 0, 7]
+
+
+def test_batch_and_graph_argument_errors():
+    a = pfac.pfac_build([b"ab"], 256)
+    L = pfac.lib()
+    cnt = C.c_uint64(0)
+    # offsets missing while packets are claimed; count pointer missing
+    assert L.pfac_scan_batch(a.handle, None, None, 3, 10, None, 0, C.byref(cnt), None) == pfac.PFAC_EINVAL
+    assert L.pfac_scan_batch_async(a.handle, None, None, 0, 0, None, 0, None, None) == pfac.PFAC_EINVAL
+    g = C.c_void_p(123)
+    # NULL stream, NULL buffers: rejected before any device work, *out cleared
+    assert L.pfac_graph_create(a.handle, None, None, 10, 0, None, 0, None, None, None,
+                               C.byref(g)) == pfac.PFAC_EINVAL
+    assert g.value is None
+    assert L.pfac_graph_launch(None, None) == pfac.PFAC_EINVAL
+    L.pfac_graph_destroy(None)
