@@ -33,6 +33,8 @@ WORKLOADS = {
     "uniform_256": "1 MiB uniform text, 100 patterns (4-16 bytes), alphabet 256, 1,000 plants",
     "dna_4": ("1 GiB order-2 Markov DNA text (codes 0-3), 10,000 patterns (8-32), "
               "alphabet 4, one plant per MiB"),
+    "packets_256": ("65,536 packets (64/576/1500 B at 40/20/40 %, 80 % printable), 20,000 "
+                    "patterns (4-128 B, heads from a depth-6 branching-3 tree), alphabet 256"),
 }
 
 KERNEL_SOURCES = ["paper_1704_02272_amd/csrc/kernels_scan.hip",
@@ -70,7 +72,7 @@ def load_traffic(workload: str, algo: str):
 def make_workload(name: str):
     from paper_1704_02272_amd import workloads as W
     return {"printable_256": W.printable_256, "uniform_256": W.uniform_256,
-            "dna_4": W.dna_4}[name]()
+            "dna_4": W.dna_4, "packets_256": W.packets_256}[name]()
 
 
 def cpu_baseline(w, budget_s: float):
@@ -92,6 +94,126 @@ def cpu_baseline(w, budget_s: float):
                       "with OpenMP chunks" % (w.name, n, reps, t_total)}
 
 
+def bench_packets(args, w):
+    """Packet batch: one persistent launch pair per batch (eager, and replayed from a
+    captured graph) against one plain launch per packet, all on one stream."""
+    import ctypes as C
+
+    import numpy as np
+    import torch
+
+    import paper_1704_02272_amd.pfac as pfac
+
+    dev = torch.device("cuda:0")
+    n = int(w.offsets[-1])
+    a = pfac.pfac_build(w.patterns, w.alphabet)
+    data = [torch.from_numpy(w.data).to(dev) for _ in range(max(1, args.copies))]
+    offs = torch.from_numpy(w.offsets.view(np.int64)).to(dev)
+    tuning = None
+    if not args.no_tune:
+        tuning = pfac.pfac_tune(a, data[0], offs, reps=5)
+    first = pfac.pfac_scan_batch(a, data[0], offs)
+    count = int(first.numel())
+    keys = torch.empty(max(count, 1), dtype=torch.int64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.Stream()
+    sizes = torch.tensor([n, w.n_packets], dtype=torch.int64, device=dev)
+
+    def timed(fn):
+        with torch.cuda.stream(stream):
+            for i in range(args.warmup):
+                fn(i)
+            stream.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                ev[i][0].record(stream)
+                fn(i)
+                ev[i][1].record(stream)
+            stream.synchronize()
+            wall = (time.perf_counter() - t0) / args.steps
+        if int(cnt.item()) != count:
+            raise RuntimeError("match count changed: %d vs %d" % (int(cnt.item()), count))
+        return wall * 1e3, [s.elapsed_time(e) for s, e in ev]
+
+    eager_ms, eager_ev = timed(lambda i: pfac.pfac_scan_batch_async(a, data[i % len(data)], offs, keys, cnt,
+                                                                     stream))
+    graphs = [pfac.pfac_graph_create(a, d, offs, keys, cnt, sizes, stream) for d in data]
+    graph_ms, graph_ev = timed(lambda i: graphs[i % len(graphs)].launch(stream))
+
+    # baseline: one plain scan (count, offsets, emit launches) per packet, on one stream
+    base = pfac.pfac_build(w.patterns, w.alphabet)
+    pfac.pfac_set_tuning(base, algo="plain")
+    slot = 16
+    bkeys = torch.empty(w.n_packets * slot, dtype=torch.int64, device=dev)
+    bcnt = torch.zeros(w.n_packets, dtype=torch.int64, device=dev)
+    L = pfac.lib()
+    h = C.c_void_p(base.handle)
+    sh = C.c_void_p(stream.cuda_stream)
+    d0, k0, c0 = data[0].data_ptr(), bkeys.data_ptr(), bcnt.data_ptr()
+    lo = [int(x) for x in w.offsets]
+
+    def per_packet():
+        for i in range(w.n_packets):
+            rc = L.pfac_scan_async(h, C.c_void_p(d0 + lo[i]), lo[i + 1] - lo[i], C.c_void_p(k0 + 8 * slot * i),
+                                   slot, C.c_void_p(c0 + 8 * i), sh)
+            if rc:
+                raise pfac.PfacError(rc, "pfac_scan_async")
+
+    base_steps = max(1, min(args.steps, args.baseline_steps))
+    with torch.cuda.stream(stream):
+        per_packet()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(base_steps):
+            per_packet()
+        stream.synchronize()
+        base_ms = (time.perf_counter() - t0) * 1e3 / base_steps
+    if int(bcnt.sum().item()) != count:
+        raise RuntimeError("per-packet scans disagree with the batch: %d vs %d"
+                           % (int(bcnt.sum().item()), count))
+    gbit = 8.0 * n / (graph_ms / 1e3) / 1e9
+    kern_s = float(np.mean(graph_ev)) / 1e3
+    alg_bytes = n + 8.0 * (w.n_packets + 1) + 8.0 * count
+    achieved = alg_bytes / kern_s / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbit, 2), "unit": "Gbit/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded numpy generator; see DESIGN.md input recipe)",
+        "config": {"workload": "packets_256", "description": WORKLOADS["packets_256"],
+                   "packets": w.n_packets, "bytes": n, "patterns": len(w.patterns),
+                   "matches": count, "tuning": tuning, "text_copies_rotated": len(data)},
+        "batch": {"graph_ms": round(graph_ms, 4), "eager_ms": round(eager_ms, 4),
+                  "graph_event_ms_mean": round(float(np.mean(graph_ev)), 4),
+                  "eager_event_ms_mean": round(float(np.mean(eager_ev)), 4),
+                  "per_packet_plain_ms": round(base_ms, 3), "per_packet_steps": base_steps,
+                  "speedup_graph_vs_per_packet": round(base_ms / graph_ms, 1),
+                  "per_packet_gbit_s": round(8.0 * n / (base_ms / 1e3) / 1e9, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic("packets_256", "tiled"),
+                     "kernel_ms_mean": round(kern_s * 1e3, 4),
+                     "algorithmic_bytes_per_launch": int(alg_bytes)},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        from oracle import native
+        ac = native.AhoCorasick(w.patterns, w.alphabet)
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < args.cpu_budget and reps < 50:
+            ac.scan_packets(w.data, w.offsets)
+            reps += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(8.0 * n * reps / el / 1e9, 3), "unit": "Gbit/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "whole batch x %d, %.1f s, textbook Aho-Corasick per packet, "
+                                         "one thread" % (reps, el)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +224,9 @@ def main():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="packets: skip the autotuner")
+    ap.add_argument("--baseline-steps", type=int, default=3,
+                    help="packets: timed passes of the per-packet baseline")
     ap.add_argument("--mode", default="scan", choices=["scan", "copy"],
                     help="copy: a plain device-to-device copy of the workload's text, the "
                          "reference that scales the HBM byte counters of the scan")
@@ -119,6 +244,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = make_workload(args.workload)
+    if args.workload == "packets_256":
+        bench_packets(args, w)
+        return
     n = len(w.text)
     a = pfac.pfac_build(w.patterns, w.alphabet)
     info = pfac.pfac_table_info(a)

@@ -51,6 +51,7 @@ extern "C" {
 #define PFAC_ENODEVICE (-8)      /* no usable gfx950 device                             */
 #define PFAC_EFORMAT (-9)        /* serialized automaton is malformed or truncated      */
 #define PFAC_ETIMEOUT (-10)      /* a device-side bounded wait expired (internal error) */
+#define PFAC_EINTERNAL (-11)     /* an internal consistency check failed               */
 
 /* Human-readable name of a status code (static storage, never NULL). */
 PFAC_API const char *pfac_strerror(int status);
@@ -145,6 +146,37 @@ PFAC_API int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t 
 PFAC_API int pfac_scan(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
                        uint64_t cap, uint64_t *h_count, void *stream);
 
+/* ------------------------------------------------------------------- host texts
+ * pfac_scan_host -- scan n bytes of host memory (texts of any length, also past 2^32).
+ * The text goes to the device in chunks of chunk_bytes (0 = 64 MiB), each sent with the
+ * next (longest pattern - 1) bytes so that matches crossing a chunk end are found (the
+ * overlap rule of Section 2.2), and each chunk keeps only matches that start inside it.
+ * Two chunks are in flight at once on two library-owned streams: the copy of one
+ * overlaps the scan of the other. A text in pinned memory (hipHostMalloc) is copied
+ * straight from the caller's buffer; pageable text is staged through pinned buffers.
+ * Runs on the current device and returns when done.
+ *   out   receives a library-allocated array of matches sorted by (start, pattern_id),
+ *         starts as 64-bit text offsets; free it with pfac_matches_free. On error
+ *         out->matches is NULL and out->count 0.
+ * Errors: PFAC_EINVAL (NULL out or automaton, NULL text with n > 0), PFAC_ETOO_LARGE
+ * (chunk_bytes + longest pattern >= 2^32), PFAC_ENODEVICE, PFAC_ENOMEM, PFAC_EHIP. */
+typedef struct {
+    uint64_t start;
+    uint32_t pattern_id;
+    uint32_t reserved; /* 0 */
+} pfac_match;
+
+typedef struct {
+    pfac_match *matches;
+    uint64_t count;
+} pfac_matches;
+
+PFAC_API int pfac_scan_host(pfac_automaton *a, const uint8_t *h_text, uint64_t n, uint64_t chunk_bytes,
+                            pfac_matches *out);
+
+/* Free the array of a pfac_matches (and zero it). NULL is a no-op. */
+PFAC_API void pfac_matches_free(pfac_matches *m);
+
 /* ------------------------------------------------------------------- packet batches
  * pfac_scan_batch_async -- scan a batch of packets held back to back in device memory
  * (CSR): packet i is d_bytes[d_offsets[i] .. d_offsets[i+1]), with d_offsets[0] = 0,
@@ -196,24 +228,55 @@ PFAC_API int pfac_graph_launch(pfac_graph *g, void *stream);
 PFAC_API void pfac_graph_destroy(pfac_graph *g);
 
 /* ------------------------------------------------------------------- tuning
- * Launch choices of an automaton's scans. None of them changes any result.
- *   algo  PFAC_ALGO_AUTO (= TILED), PFAC_ALGO_PLAIN (one lane per start, trie walked
- *         from the root in HBM, count pass + emit pass: the design of Section 2.3 as
- *         printed, kept as a baseline), PFAC_ALGO_TILED (persistent tiled kernel with
- *         the LDS prefilter and root image).
- *   grid  workgroups of the persistent tiled kernel (0 = as many as fit on the device).
- * Errors: PFAC_EINVAL. */
+ * Launch choices of an automaton's scans. None of them changes any result (positions
+ * per thread are a free parameter of the method, Section 2.3).
+ *   algo        PFAC_ALGO_AUTO (= TILED), PFAC_ALGO_PLAIN (one lane per start, trie walked
+ *               from the root in HBM, count pass + emit pass: the design of Section 2.3
+ *               as printed, kept as a baseline; single texts only), PFAC_ALGO_TILED
+ *               (persistent count kernel with the LDS prefilter and root image, then the
+ *               placement kernel).
+ *   grid        workgroups of the count kernel (0 = as many as are resident at once).
+ *   span_log2   log2 of the bytes one wave scans as a unit (its chunk): 10..16, 0 = 14.
+ *               Smaller spans spread small batches over more waves; each span costs
+ *               2 KiB of per-stream scratch.
+ *   root_depth  trie levels folded into the LDS root image (1..min(shortest pattern, 2),
+ *               or ..8 for alphabets <= 4); 0 = the builder's choice.
+ *   filter_k    symbols per LDS prefilter key (root_depth..min(longest pattern, 4), or ..16
+ *               for alphabets <= 4); 0 = the builder's choice for the root depth.
+ * pfac_set_tuning with a new root_depth or filter_k rebuilds the LDS image and uploads it
+ * to every device holding a copy; scans already queued and graphs already captured keep
+ * the image and tuning they were launched or recorded with (old images are freed by
+ * pfac_destroy). Calls that change the tuning must not race with scans of the same
+ * automaton from other host threads. pfac_get_tuning reports the values in force
+ * (root_depth and filter_k as built, never 0). Errors: PFAC_EINVAL (a field out of
+ * range; the previous tuning stays), PFAC_ENOMEM, PFAC_EHIP. */
 #define PFAC_ALGO_AUTO 0u
 #define PFAC_ALGO_PLAIN 1u
 #define PFAC_ALGO_TILED 2u
 typedef struct {
     uint32_t algo;
     uint32_t grid;
-    uint32_t reserved[6];
+    uint32_t span_log2;
+    uint32_t root_depth;
+    uint32_t filter_k;
+    uint32_t reserved[3];
 } pfac_tuning;
 
 PFAC_API int pfac_set_tuning(pfac_automaton *a, const pfac_tuning *t);
 PFAC_API int pfac_get_tuning(const pfac_automaton *a, pfac_tuning *t);
+
+/* pfac_tune -- measure the tiled scan on a sample workload already in device memory (a
+ * text when d_offsets is NULL, else a packet batch as in pfac_scan_batch) and keep the
+ * fastest tuning: coordinate descent over span_log2, then root_depth, then filter_k, then
+ * grid, each point timed with HIP events over `reps` scans (0 = 5) after one warm-up, on
+ * `stream`. Every point must reproduce the match count of the first scan, else
+ * PFAC_EINTERNAL. The tuner allocates its own key buffer (freed on return) and may grow
+ * the stream's scratch. On success the automaton keeps the best point, *out receives it
+ * (as pfac_get_tuning) and *out_ms (if not NULL) its mean milliseconds per scan; on error
+ * the previous tuning is restored. No other host thread may scan with this automaton
+ * while it runs. */
+PFAC_API int pfac_tune(pfac_automaton *a, const uint8_t *d_bytes, uint64_t n_bytes, const uint64_t *d_offsets,
+                       uint32_t n_pkts, uint32_t reps, void *stream, pfac_tuning *out, float *out_ms);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,7 @@ inline uint32_t filter_key(const uint8_t *p, uint32_t k, bool pack2) {
     return key;
 }
 
-void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
+void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, uint32_t reqD, uint32_t reqK) {
     DevTable &t = a->shape;
     t.pack2 = a->alphabet <= 4 ? 1 : 0;
     const uint32_t bits = t.pack2 ? 2 : 8;
@@ -60,7 +60,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
     }
     const uint32_t dmax = t.pack2 ? 8 : 2;
     const uint32_t kmax = t.pack2 ? 16 : 4;
-    const uint32_t D = std::min(a->min_len, dmax);
+    const uint32_t D = reqD ? reqD : std::min(a->min_len, dmax);
     t.root_depth = D;
     t.root_bits = D * bits;
     t.root_base = a->depth_start[D];
@@ -75,7 +75,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
     const uint32_t kcap = std::min(kmax, a->max_len);
     uint32_t K = D;
     double best = 1e30;
-    for (uint32_t k = D; k <= kcap; k++) {
+    for (uint32_t k = reqK ? reqK : D; k <= (reqK ? reqK : kcap); k++) {
         std::vector<uint32_t> sk, lk;
         for (uint32_t j = 0; j < a->n_pats; j++) {
             if (a->pat_len[j] < k) sk.push_back(root_key(P[j], D, bits));
@@ -134,6 +134,24 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P) {
 }
 
 }  // namespace
+
+int rebuild_lds_image(pfac_automaton *a, uint32_t D, uint32_t K) {
+    if (!a || a->n_pats == 0) return (D || K) ? PFAC_EINVAL : PFAC_OK;
+    const bool pack2 = a->alphabet <= 4;
+    const uint32_t dmax = std::min(a->min_len, pack2 ? 8u : 2u);
+    const uint32_t kmax = std::min(a->max_len, pack2 ? 16u : 4u);
+    if (D > dmax) return PFAC_EINVAL;
+    const uint32_t d = D ? D : dmax;
+    if (K && (K < d || K > kmax)) return PFAC_EINVAL;
+    std::vector<const uint8_t *> P(a->n_pats);
+    for (uint32_t j = 0; j < a->n_pats; j++) P[j] = a->pat_bytes.data() + a->pat_off[j];
+    try {
+        build_lds_image(a, P, D, K);
+    } catch (const std::bad_alloc &) {
+        return PFAC_ENOMEM;
+    }
+    return PFAC_OK;
+}
 
 int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
                     uint32_t alphabet, pfac_automaton **out) {
@@ -250,7 +268,11 @@ int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n
         t.n_nodes = a->n_nodes;
         t.min_len = minl;
         t.max_len = maxl;
-        build_lds_image(a, P);
+        a->pat_off.assign(n_pats + 1, 0);
+        for (uint32_t j = 0; j < n_pats; j++) a->pat_off[j + 1] = a->pat_off[j] + lens[j];
+        a->pat_bytes.resize(a->pat_off[n_pats]);
+        for (uint32_t j = 0; j < n_pats; j++) memcpy(a->pat_bytes.data() + a->pat_off[j], P[j], lens[j]);
+        build_lds_image(a, P, 0, 0);
         (void)total;
     } catch (const std::bad_alloc &) {
         delete a;

@@ -21,6 +21,7 @@ extern "C" const char *pfac_strerror(int status) {
         case PFAC_ENODEVICE: return "no usable gfx950 device";
         case PFAC_EFORMAT: return "malformed serialized automaton";
         case PFAC_ETIMEOUT: return "device-side wait timed out";
+        case PFAC_EINTERNAL: return "internal consistency check failed";
         default: return "unknown status";
     }
 }

@@ -7,7 +7,7 @@
 //
 // Count kernel (scan_count), one persistent wave per span at a time, no wave ever
 // waiting on another:
-//  * Spans. The text is cut into kSpan-byte spans; wave g of G takes spans g, g+G, ...
+//  * Spans. The text is cut into spans of 2^span_log2 bytes (1-64 KiB, a tuning choice); wave g of G takes spans g, g+G, ...
 //    and streams each in 1 KiB steps: 64 lanes x 16 bytes, one 16-byte load per lane,
 //    the next three steps' loads already in flight.
 //  * LDS prefilter. No pattern is shorter than min_len, so a start can only match if its
@@ -520,13 +520,15 @@ struct Scanner {
 template <int LAYOUT, bool PACK2, bool SEG>
 __global__ __launch_bounds__(kThreads) void scan_count(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
                                                       const uint64_t *__restrict__ offsets, uint32_t n_packets,
-                                                      SpanOut so, const uint64_t *__restrict__ sizes) {
+                                                      SpanOut so, const uint64_t *__restrict__ sizes,
+                                                      uint32_t span_log2) {
     __shared__ __align__(16) uint32_t img[kLdsWords];
     if (sizes) {  // sizes of this batch, bounded by those the launch was set up for
         n = sizes[0] < n ? sizes[0] : n;
         n_packets = sizes[1] < n_packets ? (uint32_t)sizes[1] : n_packets;
     }
-    const uint32_t n_spans = (uint32_t)((n + kSpan - 1) / kSpan);
+    const uint64_t span_len = 1ull << span_log2;
+    const uint32_t n_spans = (uint32_t)((n + span_len - 1) >> span_log2);
     {
         // filter words to offset 0, root bitmap and rank table to their fixed places
         const uint32_t fw = t.root_word, rw = t.rank_word - t.root_word, kw = t.short_word - t.rank_word,
@@ -544,8 +546,8 @@ __global__ __launch_bounds__(kThreads) void scan_count(DevTable t, const uint8_t
                                    offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0};
     const uint32_t waves = gridDim.x * kWaves;
     for (uint32_t span = blockIdx.x * kWaves + wave; span < n_spans; span += waves) {
-        SpanState S{(uint64_t)span * kSpan, span, 0, 0, kNone, 0};
-        const uint64_t hi = S.a + kSpan < n ? S.a + kSpan : n;
+        SpanState S{(uint64_t)span << span_log2, span, 0, 0, kNone, 0};
+        const uint64_t hi = S.a + span_len < n ? S.a + span_len : n;
         sc.stream(S, hi);
         const uint64_t total = wave_sum64(S.my_cnt);
         if (lane == 0) {
@@ -565,14 +567,15 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                                                            const uint64_t *__restrict__ offsets, uint32_t n_packets,
                                                            uint64_t *__restrict__ keys, uint64_t cap,
                                                            uint64_t *__restrict__ d_count, SpanOut so, TileState ts,
-                                                           const uint64_t *__restrict__ sizes) {
+                                                           const uint64_t *__restrict__ sizes, uint32_t span_log2) {
     __shared__ uint64_t span_off[kBlockSpans];
     __shared__ uint32_t sh[4];
     if (sizes) {
         n = sizes[0] < n ? sizes[0] : n;
         n_packets = sizes[1] < n_packets ? (uint32_t)sizes[1] : n_packets;
     }
-    const uint32_t n_spans = (uint32_t)((n + kSpan - 1) / kSpan);
+    const uint64_t span_len = 1ull << span_log2;
+    const uint32_t n_spans = (uint32_t)((n + span_len - 1) >> span_log2);
     const uint32_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const Trie<LAYOUT> T{t};
@@ -655,8 +658,8 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             const uint32_t sp = blk * kBlockSpans + i;
             if (sp >= n_spans || so.cnt[sp] == 0) continue;
             uint64_t run = span_off[i];
-            const uint64_t a = (uint64_t)sp * kSpan;
-            const uint64_t b = a + kSpan < n ? a + kSpan : n;
+            const uint64_t a = (uint64_t)sp << span_log2;
+            const uint64_t b = a + span_len < n ? a + span_len : n;
             const uint32_t nh = so.nh[sp], ovf = so.ovf[sp];
             for (uint32_t h0 = 0; h0 < nh; h0 += 64) {
                 const bool on = h0 + lane < nh;
@@ -737,8 +740,8 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
 template <int LAYOUT, bool PACK2, bool SEG>
 int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-               const uint64_t *sizes, uint32_t grid, hipStream_t s) {
-    const uint64_t n_spans = (n + kSpan - 1) / kSpan;
+               const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s) {
+    const uint64_t n_spans = (n + (1ull << span_log2) - 1) >> span_log2;
     const uint64_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
     auto kc = scan_count<LAYOUT, PACK2, SEG>;
     auto kp = place_emit<LAYOUT, SEG>;
@@ -763,8 +766,9 @@ int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_
     uint64_t gp = (uint64_t)cus * (uint32_t)per_cu_p;
     if (gp > n_blocks) gp = n_blocks;
     if (gp == 0) gp = 1;
-    kc<<<(uint32_t)gc, kThreads, 0, s>>>(t, text, n, offsets, n_packets, so, sizes);
-    kp<<<(uint32_t)gp, kPlaceThreads, 0, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes);
+    kc<<<(uint32_t)gc, kThreads, 0, s>>>(t, text, n, offsets, n_packets, so, sizes, span_log2);
+    kp<<<(uint32_t)gp, kPlaceThreads, 0, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes,
+                                               span_log2);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -772,12 +776,13 @@ int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_
 
 int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                  uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-                 const uint64_t *sizes, uint32_t grid, hipStream_t s) {
+                 const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s) {
+    if (span_log2 < kMinSpanLog2 || span_log2 > kMaxSpanLog2) return -1;
     const bool seg = offsets != nullptr;
     const bool narrow = t.layout == LAYOUT_NARROW;
     const bool pack2 = t.pack2 != 0;
 #define PFAC_L(LA, P2, SG) \
-    return launch_one<LA, P2, SG>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, s)
+    return launch_one<LA, P2, SG>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, span_log2, s)
     if (narrow) {
         if (pack2) { if (seg) PFAC_L(LAYOUT_NARROW, true, true); else PFAC_L(LAYOUT_NARROW, true, false); }
         else { if (seg) PFAC_L(LAYOUT_NARROW, false, true); else PFAC_L(LAYOUT_NARROW, false, false); }

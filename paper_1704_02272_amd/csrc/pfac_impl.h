@@ -88,6 +88,9 @@ struct DeviceCopy {
          *lds_image = nullptr;
     DevTable view{};
     std::map<void *, Workspace *> workspaces;  // keyed by stream
+    // LDS images replaced by a change of tuning. Queued scans and captured graphs may
+    // still read them, so they are freed with the copy, not when replaced.
+    std::vector<void *> retired;
 };
 
 }  // namespace pfac
@@ -97,6 +100,11 @@ struct pfac_automaton {
     uint32_t min_len = 0, max_len = 0;
     uint32_t layout = 0, nw = 0;  // nw: 64-bit bitmap words per node (WIDE)
     uint32_t algo = 0, grid = 0;  // tuning: kernel choice, persistent grid (0 = auto)
+    uint32_t span_log2 = 14;      // tuning: log2 of the count kernel's span length
+    uint32_t req_depth = 0, req_k = 0;  // tuning: requested root depth / filter key (0 = builder's)
+    // The patterns as given (CSR), kept to rebuild the LDS image when tuning asks.
+    std::vector<uint8_t> pat_bytes;
+    std::vector<uint64_t> pat_off;
     // Paper layout (Section 3.1): first-child offset and the bitmap in 64-bit words.
     std::vector<uint32_t> first_child;
     std::vector<uint64_t> bitmap;      // n_nodes * nbw, nbw = ceil(alphabet / 64)
@@ -117,4 +125,7 @@ namespace pfac {
 int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
                     uint32_t alphabet, pfac_automaton **out);
 void release_device_copies(pfac_automaton *a);
+// Rebuild the LDS image with root depth D and filter key length K (0 = the builder's
+// choice for either). PFAC_EINVAL when D or K is outside what the pattern set allows.
+int rebuild_lds_image(pfac_automaton *a, uint32_t D, uint32_t K);
 }  // namespace pfac

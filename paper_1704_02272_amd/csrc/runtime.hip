@@ -93,6 +93,7 @@ void free_copy(DeviceCopy *c) {
     hipFree(c->out_first);
     hipFree(c->out_ids);
     hipFree(c->lds_image);
+    for (void *p : c->retired) hipFree(p);
     hipSetDevice(prev);
     delete c;
 }
@@ -143,9 +144,10 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     return PFAC_OK;
 }
 
-static int ensure_tiles(Workspace *w, uint64_t n, void *stream);
+static int ensure_tiles(Workspace *w, uint64_t n, uint32_t span_log2, void *stream);
 
-static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo, Workspace **out) {
+static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo, uint32_t span_log2,
+                         Workspace **out) {
     Workspace *&w = c->workspaces[stream];
     if (!w) {
         w = new (std::nothrow) Workspace();
@@ -156,7 +158,7 @@ static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo,
             return PFAC_ENOMEM;
     }
     if (algo == PFAC_ALGO_TILED) {
-        const int rc = ensure_tiles(w, n, stream);
+        const int rc = ensure_tiles(w, n, span_log2, stream);
         if (rc) return rc;
         *out = w;
         return PFAC_OK;
@@ -204,8 +206,8 @@ namespace pfac {
 
 // Tiled-path scratch for n bytes in workspace w (grown on demand; the stream is drained
 // before old buffers are freed). Clears the look-back words before the epoch could wrap.
-static int ensure_tiles(Workspace *w, uint64_t n, void *stream) {
-    const uint64_t ns = (n + kSpan - 1) / kSpan;
+static int ensure_tiles(Workspace *w, uint64_t n, uint32_t span_log2, void *stream) {
+    const uint64_t ns = (n + (1ull << span_log2) - 1) >> span_log2;
     if (ns > w->cap_spans || !w->ts.ctrl) {
         if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
         free_tiles(w);
@@ -249,7 +251,7 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, co
     const bool batch = d_offsets != nullptr;
     const uint32_t algo = (a->algo == PFAC_ALGO_PLAIN && !batch) ? PFAC_ALGO_PLAIN : PFAC_ALGO_TILED;
     Workspace *w = nullptr;
-    rc = get_workspace(c, stream, n, algo, &w);
+    rc = get_workspace(c, stream, n, algo, a->span_log2, &w);
     if (rc) return rc;
     if (ws_out) *ws_out = w;
     uint64_t *cnt = d_count ? d_count : w->d_count;
@@ -259,9 +261,10 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, co
             return PFAC_EHIP;
         return PFAC_OK;
     }
-    const uint64_t ns = (n + kSpan - 1) / kSpan;
+    const uint64_t ns = (n + (1ull << a->span_log2) - 1) >> a->span_log2;
     const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, (ns + kWaves - 1) / kWaves) : 0u;
-    if (launch_tiled(c->view, d_text, n, d_offsets, n_pkts, d_keys, cap, cnt, w->so, w->ts, nullptr, grid, s))
+    if (launch_tiled(c->view, d_text, n, d_offsets, n_pkts, d_keys, cap, cnt, w->so, w->ts, nullptr, grid,
+                     a->span_log2, s))
         return PFAC_EHIP;
     w->launches++;
     return PFAC_OK;
@@ -348,8 +351,11 @@ extern "C" int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, cons
     if (!g) return PFAC_ENOMEM;
     g->a = a;
     DevTable view{};
+    uint32_t span_log2 = kSpanLog2, grid = 0;
     {
         std::lock_guard<std::mutex> lk(a->mu);
+        span_log2 = a->span_log2;
+        grid = a->grid;
         DeviceCopy *c = nullptr;
         int rc = get_copy(a, &c);
         if (rc) {
@@ -360,12 +366,12 @@ extern "C" int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, cons
         view = c->view;
     }
     // everything that allocates happens before the capture
-    int rc = ensure_tiles(&g->ws, max_bytes, stream);
+    int rc = ensure_tiles(&g->ws, max_bytes, span_log2, stream);
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = PFAC_EHIP;
     if (!rc && hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = PFAC_EHIP;
     if (!rc) {
         const int lr = launch_tiled(view, d_bytes, max_bytes, d_offsets, d_offsets ? max_pkts : 0, d_keys, cap,
-                                    d_count, g->ws.so, g->ws.ts, d_sizes, a->grid, s);
+                                    d_count, g->ws.so, g->ws.ts, d_sizes, grid, span_log2, s);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(s, &graph);
         g->graph = graph;
@@ -395,13 +401,64 @@ extern "C" int pfac_graph_launch(pfac_graph *g, void *stream) {
 
 extern "C" void pfac_graph_destroy(pfac_graph *g) { graph_free(g); }
 
-extern "C" int pfac_set_tuning(pfac_automaton *a, const pfac_tuning *t) {
-    if (!a || !t) return PFAC_EINVAL;
+// Give every device copy the new LDS image after the host image changed. The old image
+// is retired, not freed: queued scans and captured graphs keep reading it.
+static int reupload_lds_images(pfac_automaton *a) {
+    if (a->copies.empty()) return PFAC_OK;  // nothing on any device yet
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return PFAC_EHIP;
+    int rc = PFAC_OK;
+    for (DeviceCopy *c : a->copies) {
+        if (hipSetDevice(c->device) != hipSuccess) {
+            rc = PFAC_EHIP;
+            break;
+        }
+        void *img = nullptr;
+        rc = upload_vec(a->lds_image, &img);
+        if (rc) {
+            hipFree(img);
+            break;
+        }
+        c->retired.push_back(c->lds_image);
+        c->lds_image = img;
+        DevTable v = a->shape;
+        v.nodes = c->view.nodes;
+        v.bm = c->view.bm;
+        v.out_first = c->view.out_first;
+        v.out_ids = c->view.out_ids;
+        v.lds_image = (const uint32_t *)c->lds_image;
+        c->view = v;
+    }
+    (void)hipSetDevice(prev);
+    return rc;
+}
+
+static int set_tuning_locked(pfac_automaton *a, const pfac_tuning *t) {
     if (t->algo > PFAC_ALGO_TILED) return PFAC_EINVAL;
-    std::lock_guard<std::mutex> g(a->mu);
+    const uint32_t span = t->span_log2 ? t->span_log2 : kSpanLog2;
+    if (span < kMinSpanLog2 || span > kMaxSpanLog2) return PFAC_EINVAL;
+    if (t->root_depth != a->req_depth || t->filter_k != a->req_k) {
+        int rc = rebuild_lds_image(a, t->root_depth, t->filter_k);
+        if (rc) {
+            // keep the previous image in force
+            (void)rebuild_lds_image(a, a->req_depth, a->req_k);
+            return rc;
+        }
+        a->req_depth = t->root_depth;
+        a->req_k = t->filter_k;
+        rc = reupload_lds_images(a);
+        if (rc) return rc;
+    }
     a->algo = t->algo;
     a->grid = t->grid;
+    a->span_log2 = span;
     return PFAC_OK;
+}
+
+extern "C" int pfac_set_tuning(pfac_automaton *a, const pfac_tuning *t) {
+    if (!a || !t) return PFAC_EINVAL;
+    std::lock_guard<std::mutex> g(a->mu);
+    return set_tuning_locked(a, t);
 }
 
 extern "C" int pfac_get_tuning(const pfac_automaton *a, pfac_tuning *t) {
@@ -409,5 +466,158 @@ extern "C" int pfac_get_tuning(const pfac_automaton *a, pfac_tuning *t) {
     memset(t, 0, sizeof(*t));
     t->algo = a->algo == PFAC_ALGO_PLAIN ? PFAC_ALGO_PLAIN : PFAC_ALGO_TILED;
     t->grid = a->grid;
+    t->span_log2 = a->span_log2;
+    t->root_depth = a->shape.root_depth;
+    t->filter_k = a->shape.filter_k ? a->shape.filter_k : a->shape.root_depth;
     return PFAC_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+struct TuneRun {
+    pfac_automaton *a;
+    const uint8_t *d_bytes;
+    uint64_t n;
+    const uint64_t *d_offsets;
+    uint32_t n_pkts;
+    uint32_t reps;
+    hipStream_t s;
+    uint64_t *d_keys = nullptr, cap = 0, *d_count = nullptr;
+    uint64_t want = ~0ull;  // the match count every candidate must reproduce
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+int tune_enqueue(TuneRun &r) {
+    if (r.d_offsets)
+        return scan_enqueue(r.a, r.d_bytes, r.n, r.d_offsets, r.n_pkts, r.d_keys, r.cap, r.d_count, r.s, nullptr);
+    return scan_enqueue(r.a, r.d_bytes, r.n, nullptr, 0, r.d_keys, r.cap, r.d_count, r.s, nullptr);
+}
+
+// Mean milliseconds per scan under the automaton's current tuning (one warm-up scan, then
+// `reps` timed). Checks that the count is the one every other candidate produced.
+int tune_measure(TuneRun &r, float *ms) {
+    int rc = tune_enqueue(r);
+    if (rc) return rc;
+    if (hipEventRecord(r.e0, r.s) != hipSuccess) return PFAC_EHIP;
+    for (uint32_t i = 0; i < r.reps; i++)
+        if ((rc = tune_enqueue(r))) return rc;
+    if (hipEventRecord(r.e1, r.s) != hipSuccess || hipEventSynchronize(r.e1) != hipSuccess) return PFAC_EHIP;
+    float t = 0;
+    if (hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) return PFAC_EHIP;
+    uint64_t cnt = 0;
+    if (hipMemcpy(&cnt, r.d_count, 8, hipMemcpyDeviceToHost) != hipSuccess) return PFAC_EHIP;
+    if (cnt == kCountTimeout) return PFAC_ETIMEOUT;
+    if (cnt != r.want) return PFAC_EINTERNAL;
+    *ms = t / (float)r.reps;
+    return PFAC_OK;
+}
+
+int tune_try(TuneRun &r, const pfac_tuning &cand, float *ms) {
+    {
+        std::lock_guard<std::mutex> g(r.a->mu);
+        int rc = set_tuning_locked(r.a, &cand);
+        if (rc) return rc;
+    }
+    return tune_measure(r, ms);
+}
+
+}  // namespace
+
+extern "C" int pfac_tune(pfac_automaton *a, const uint8_t *d_bytes, uint64_t n_bytes, const uint64_t *d_offsets,
+                         uint32_t n_pkts, uint32_t reps, void *stream, pfac_tuning *out, float *out_ms) {
+    if (!a || !out || (n_bytes > 0 && !d_bytes) || (d_offsets == nullptr && n_pkts > 0)) return PFAC_EINVAL;
+    if (n_bytes >= (1ull << 32)) return PFAC_ETOO_LARGE;
+    if (a->n_pats == 0 || n_bytes == 0) {
+        int rc = pfac_get_tuning(a, out);
+        if (out_ms) *out_ms = 0.f;
+        return rc;
+    }
+    TuneRun r{a, d_bytes, n_bytes, d_offsets, n_pkts, reps ? reps : 5, (hipStream_t)stream};
+    int rc = PFAC_OK;
+    pfac_tuning start{};
+    (void)pfac_get_tuning(a, &start);
+    start.root_depth = a->req_depth;  // as requested, so restoring keeps the builder's choice
+    start.filter_k = a->req_k;
+    // the match count under the current tuning sizes the key buffer and is the answer
+    // every candidate has to reproduce
+    if (hipMalloc(&r.d_count, 8) != hipSuccess) return PFAC_ENOMEM;
+    if (hipEventCreate(&r.e0) != hipSuccess || hipEventCreate(&r.e1) != hipSuccess) rc = PFAC_EHIP;
+    if (!rc) rc = tune_enqueue(r);
+    if (!rc && hipMemcpyAsync(&r.want, r.d_count, 8, hipMemcpyDeviceToHost, r.s) != hipSuccess) rc = PFAC_EHIP;
+    if (!rc && hipStreamSynchronize(r.s) != hipSuccess) rc = PFAC_EHIP;
+    if (!rc && (r.want == kCountTimeout || r.want == kCountOverflow)) rc = PFAC_ETIMEOUT;
+    if (!rc) {
+        r.cap = r.want;
+        if (r.cap && hipMalloc(&r.d_keys, r.cap * 8) != hipSuccess) rc = PFAC_ENOMEM;
+    }
+    pfac_tuning best = start;
+    best.algo = PFAC_ALGO_TILED;
+    best.root_depth = a->req_depth;
+    best.filter_k = a->req_k;
+    float best_ms = 0.f;
+    if (!rc) rc = tune_try(r, best, &best_ms);
+    // coordinate descent: span length, then root depth, then filter key, then grid
+    const bool pack2 = a->alphabet <= 4;
+    const uint32_t dmax = std::min(a->min_len, pack2 ? 8u : 2u);
+    const uint32_t kmax = std::min(a->max_len, pack2 ? 16u : 4u);
+    auto consider = [&](pfac_tuning cand) {
+        if (rc) return;
+        float ms = 0.f;
+        const int e = tune_try(r, cand, &ms);
+        if (e == PFAC_EINVAL) return;  // not a valid point for this pattern set
+        if (e) {
+            rc = e;
+            return;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    };
+    for (uint32_t sl = 11; sl <= kMaxSpanLog2; sl++) {
+        if (sl == best.span_log2) continue;
+        pfac_tuning c = best;
+        c.span_log2 = sl;
+        consider(c);
+    }
+    for (uint32_t d = 1; d <= dmax; d++) {
+        pfac_tuning c = best;
+        c.root_depth = d;
+        c.filter_k = 0;  // the builder's key length for that depth
+        consider(c);
+    }
+    {
+        const uint32_t d0 = best.root_depth ? best.root_depth : dmax;
+        for (uint32_t k = d0; k <= kmax; k++) {
+            pfac_tuning c = best;
+            c.filter_k = k;
+            consider(c);
+        }
+    }
+    {
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        for (uint32_t g : {(uint32_t)cus / 2, (uint32_t)cus * 2}) {
+            pfac_tuning c = best;
+            c.grid = g;
+            consider(c);
+        }
+    }
+    // leave the automaton at the best point (or where it started, on error)
+    {
+        std::lock_guard<std::mutex> g(a->mu);
+        const int e = set_tuning_locked(a, rc ? &start : &best);
+        if (!rc) rc = e;
+    }
+    if (r.e0) hipEventDestroy(r.e0);
+    if (r.e1) hipEventDestroy(r.e1);
+    hipFree(r.d_keys);
+    hipFree(r.d_count);
+    if (!rc) {
+        (void)pfac_get_tuning(a, out);
+        if (out_ms) *out_ms = best_ms;
+    }
+    return rc;
 }

@@ -11,14 +11,15 @@ namespace pfac {
 constexpr uint32_t kThreads = 1024;  // workgroup: 16 waves sharing one LDS image
 constexpr uint32_t kWaves = kThreads / 64;
 constexpr uint32_t kStep = 1024;     // bytes a wave streams per step: 64 lanes x 16
-constexpr uint32_t kSpan = 16384;    // bytes per work unit (a wave's ticket)
+constexpr uint32_t kSpanLog2 = 14;   // default bytes per work unit (a wave's span): 16 KiB
+constexpr uint32_t kMinSpanLog2 = 10; // a span holds at least one 1 KiB wave step
+constexpr uint32_t kMaxSpanLog2 = 16; // span-local starts are 16-bit
 constexpr uint32_t kQCap = 2048;     // survivor queue; walked when a step might not fit, and at the span end
 constexpr uint32_t kHCap = 256;      // match records kept per span
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
 constexpr uint32_t kPlaceThreads = 256;
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
 constexpr uint32_t kWaveLds = kQCap * 2;  // bytes of LDS per wave (survivor queue)
-static_assert(kSpan <= 65536, "span-local starts are 16-bit");
 static_assert(kWaveLds % 16 == 0, "wave regions stay 16-byte aligned");
 
 // Fixed LDS layout of the scan kernel (32-bit words): the filter at offset 0 so a probe's
@@ -72,9 +73,11 @@ constexpr uint64_t kCountOverflow = ~0ull - 1;
 // Count kernel then placement kernel on stream s. offsets: packet offsets (n_packets + 1)
 // or null for one text. sizes: null, or device {n, n_packets} read at run time and
 // bounded by the n / n_packets given here (graph replays). grid: workgroups of the
-// count kernel (0 = as many as are resident at once).
+// count kernel (0 = as many as are resident at once). span_log2: log2 of the span length,
+// kMinSpanLog2..kMaxSpanLog2 (else -1, nothing launched); the scratch in `so` must hold
+// ceil(n / 2^span_log2) spans.
 int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                  uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-                 const uint64_t *sizes, uint32_t grid, hipStream_t s);
+                 const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s);
 
 }  // namespace pfac

@@ -30,6 +30,7 @@ PFAC_ECAPACITY = -7
 PFAC_ENODEVICE = -8
 PFAC_EFORMAT = -9
 PFAC_ETIMEOUT = -10
+PFAC_EINTERNAL = -11
 
 _lib = None
 
@@ -49,12 +50,26 @@ class TableInfo(C.Structure):
                                   "lds_image_bytes")]
 
 
+class Match(C.Structure):
+    _fields_ = [("start", C.c_uint64), ("pattern_id", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class Matches(C.Structure):
+    _fields_ = [("matches", C.POINTER(Match)), ("count", C.c_uint64)]
+
+
+MATCH_DTYPE = np.dtype([("start", np.uint64), ("pattern_id", np.uint32), ("reserved", np.uint32)])
+
 PFAC_ALGO_AUTO, PFAC_ALGO_PLAIN, PFAC_ALGO_TILED = 0, 1, 2
 ALGOS = {"auto": PFAC_ALGO_AUTO, "plain": PFAC_ALGO_PLAIN, "tiled": PFAC_ALGO_TILED}
 
 
 class Tuning(C.Structure):
-    _fields_ = [("algo", C.c_uint32), ("grid", C.c_uint32), ("reserved", C.c_uint32 * 6)]
+    _fields_ = [("algo", C.c_uint32), ("grid", C.c_uint32), ("span_log2", C.c_uint32),
+                ("root_depth", C.c_uint32), ("filter_k", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+
+TUNING_FIELDS = ("algo", "grid", "span_log2", "root_depth", "filter_k")
 
 
 def lib():
@@ -86,8 +101,12 @@ def lib():
                                             VP, VP, VP, C.POINTER(VP)]),
             "pfac_graph_launch": (C.c_int, [VP, VP]),
             "pfac_graph_destroy": (None, [VP]),
+            "pfac_scan_host": (C.c_int, [VP, VP, C.c_uint64, C.c_uint64, C.POINTER(Matches)]),
+            "pfac_matches_free": (None, [C.POINTER(Matches)]),
             "pfac_set_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
             "pfac_get_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
+            "pfac_tune": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint32, C.c_uint32, VP,
+                                    C.POINTER(Tuning), C.POINTER(C.c_float)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -178,16 +197,40 @@ def pfac_export_outputs(a: Automaton):
     return first, ids[:info["n_patterns"]]
 
 
-def pfac_set_tuning(a: Automaton, algo: str = "auto", grid: int = 0):
-    t = Tuning(ALGOS[algo], grid)
+def pfac_set_tuning(a: Automaton, algo: str = "auto", grid: int = 0, span_log2: int = 0,
+                    root_depth: int = 0, filter_k: int = 0):
+    t = Tuning(ALGOS[algo], grid, span_log2, root_depth, filter_k)
     _check(lib().pfac_set_tuning(a.handle, C.byref(t)), "pfac_set_tuning")
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    d = {f: int(getattr(t, f)) for f in TUNING_FIELDS}
+    d["algo"] = {v: k for k, v in ALGOS.items()}[t.algo]
+    return d
 
 
 def pfac_get_tuning(a: Automaton) -> dict:
     t = Tuning()
     _check(lib().pfac_get_tuning(a.handle, C.byref(t)), "pfac_get_tuning")
-    name = {v: k for k, v in ALGOS.items()}[t.algo]
-    return {"algo": name, "grid": t.grid}
+    return _tuning_dict(t)
+
+
+def pfac_tune(a: Automaton, data, offsets=None, reps: int = 5, stream=None) -> dict:
+    """Run the library's autotuner on a device-resident sample (a text, or a packet
+    batch when ``offsets`` is given) and keep the best tuning. Returns it, with the mean
+    milliseconds per scan under ``"ms"``."""
+    data = _device_u8(data)
+    if offsets is not None:
+        offsets = _device_u64(offsets, "offsets")
+    t = Tuning()
+    ms = C.c_float(0)
+    rc = lib().pfac_tune(a.handle, _ptr(data), data.numel(), _ptr(offsets),
+                         offsets.numel() - 1 if offsets is not None else 0, reps,
+                         _stream_handle(stream), C.byref(t), C.byref(ms))
+    _check(rc, "pfac_tune")
+    d = _tuning_dict(t)
+    d["ms"] = float(ms.value)
+    return d
 
 
 def pfac_upload(a: Automaton, device: int = 0):
@@ -331,6 +374,24 @@ def key_to_packet(keys: np.ndarray, offsets: np.ndarray):
     offs = np.asarray(offsets, dtype=np.int64)
     pk = np.searchsorted(offs, starts, side="right") - 1
     return pk, starts - offs[pk], ids
+
+
+def pfac_scan_host(a: Automaton, text, chunk_bytes: int = 0) -> np.ndarray:
+    """Scan a host buffer (numpy uint8 array, or any object exposing a uint8 buffer, e.g.
+    a pinned torch CPU tensor's numpy view). Returns a structured array with fields
+    ``start`` (uint64) and ``pattern_id`` (uint32), sorted."""
+    arr = np.ascontiguousarray(np.asarray(text, dtype=np.uint8))
+    m = Matches()
+    rc = lib().pfac_scan_host(a.handle, C.c_void_p(arr.ctypes.data if arr.size else 0), arr.size,
+                              chunk_bytes, C.byref(m))
+    _check(rc, "pfac_scan_host")
+    try:
+        if m.count == 0:
+            return np.zeros(0, dtype=MATCH_DTYPE)
+        buf = C.cast(m.matches, C.POINTER(C.c_uint8 * (int(m.count) * MATCH_DTYPE.itemsize))).contents
+        return np.frombuffer(buf, dtype=MATCH_DTYPE).copy()
+    finally:
+        lib().pfac_matches_free(C.byref(m))
 
 
 def keys_to_numpy(keys) -> np.ndarray:

@@ -139,3 +139,50 @@ def test_batch_and_graph_argument_errors():
     assert g.value is None
     assert L.pfac_graph_launch(None, None) == pfac.PFAC_EINVAL
     L.pfac_graph_destroy(None)
+
+
+def test_tuning_rebuilds_lds_image_on_host():
+    pats = [b"abcdef", b"abxy", b"zzzz", b"qq12"]
+    a = pfac.pfac_build(pats, 256)
+    t0 = pfac.pfac_get_tuning(a)
+    assert t0["span_log2"] == 14 and t0["root_depth"] == 2 and t0["filter_k"] >= 2
+    pfac.pfac_set_tuning(a, span_log2=11, root_depth=1, filter_k=3)
+    t1 = pfac.pfac_get_tuning(a)
+    assert (t1["span_log2"], t1["root_depth"], t1["filter_k"]) == (11, 1, 3)
+    info = pfac.pfac_table_info(a)
+    assert info["root_depth"] == 1 and info["filter_k"] == 3
+    # out of range: shorter than the root depth, longer than the shortest pattern allows,
+    # a span outside 10..16; the previous tuning stays in force
+    for bad in (dict(root_depth=1, filter_k=5), dict(root_depth=3), dict(root_depth=2, filter_k=1),
+                dict(span_log2=9), dict(span_log2=17)):
+        with pytest.raises(pfac.PfacError) as e:
+            pfac.pfac_set_tuning(a, **bad)
+        assert e.value.code == pfac.PFAC_EINVAL
+        assert pfac.pfac_get_tuning(a) == t1
+    # back to the builder's choice
+    pfac.pfac_set_tuning(a)
+    assert pfac.pfac_get_tuning(a) == t0
+
+
+def test_tuning_cache_key_separates_workloads():
+    from paper_1704_02272_amd import tuning_cache as TC
+    k1 = TC.cache_key([b"ab"], 256, 100, 0, "dev")
+    assert k1 == TC.cache_key([b"ab"], 256, 100, 0, "dev")
+    assert len({k1, TC.cache_key([b"ab"], 256, 101, 0, "dev"), TC.cache_key([b"ab"], 4, 100, 0, "dev"),
+                TC.cache_key([b"ab", b"c"], 256, 100, 0, "dev"), TC.cache_key([b"ab"], 256, 100, 3, "dev"),
+                TC.cache_key([b"ab"], 256, 100, 0, "other")}) == 6
+
+
+def test_host_scan_argument_errors():
+    a = pfac.pfac_build([b"ab"], 256)
+    L = pfac.lib()
+    m = pfac.Matches()
+    assert L.pfac_scan_host(a.handle, None, 10, 0, C.byref(m)) == pfac.PFAC_EINVAL
+    assert L.pfac_scan_host(None, None, 0, 0, C.byref(m)) == pfac.PFAC_EINVAL
+    assert L.pfac_scan_host(a.handle, None, 0, 0, None) == pfac.PFAC_EINVAL
+    assert L.pfac_scan_host(a.handle, None, 0, (1 << 32) - 1, C.byref(m)) == pfac.PFAC_ETOO_LARGE
+    assert not m.matches and m.count == 0
+    # an empty text needs no device and returns no match
+    assert L.pfac_scan_host(a.handle, None, 0, 0, C.byref(m)) == pfac.PFAC_OK and m.count == 0
+    L.pfac_matches_free(C.byref(m))
+    L.pfac_matches_free(None)

@@ -1,0 +1,98 @@
+"""GPU parity across launch choices: span length, root depth, filter key and grid change
+only the speed, never the keys (positions per thread are a free parameter of the method).
+Also the autotuner, and captured graphs that outlive a change of tuning."""
+import itertools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1704_02272_amd.pfac as pfac  # noqa: E402
+from oracle import native  # noqa: E402
+from paper_1704_02272_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(a, dtype=torch.uint8):
+    return torch.from_numpy(np.array(a, copy=True)).to(DEV).to(dtype)
+
+
+def _case(rng, sigma, npat, n, lo, hi):
+    pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(lo, hi + 1))).astype(np.uint8))
+            for _ in range(npat)]
+    text = rng.integers(0, sigma, size=n).astype(np.uint8)
+    for _ in range(n // 512):
+        p = pats[int(rng.integers(0, npat))]
+        o = int(rng.integers(0, n - len(p)))
+        text[o:o + len(p)] = np.frombuffer(p, dtype=np.uint8)
+    return pats, text
+
+
+def test_every_tuning_point_gives_the_same_keys_bytes():
+    rng = np.random.default_rng(11)
+    pats, text = _case(rng, 256, 400, (1 << 20) + 333, 3, 40)
+    pats += [b"ab", b"abc"]          # shortest pattern 2: root depth up to 2
+    want = native.AhoCorasick(pats, 256).scan(text)
+    a = pfac.pfac_build(pats, 256)
+    t = _dev(text)
+    points = 0
+    for span, d, k in itertools.product(range(10, 17), (1, 2), (1, 2, 3, 4)):
+        if k < d:
+            continue
+        pfac.pfac_set_tuning(a, span_log2=span, root_depth=d, filter_k=k, grid=[0, 7][span % 2])
+        got = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+        assert np.array_equal(got, want), (span, d, k)
+        points += 1
+    assert points == 7 * 7
+
+
+def test_tuning_points_two_bit_symbols():
+    rng = np.random.default_rng(12)
+    pats, text = _case(rng, 4, 2000, (1 << 20) + 77, 8, 24)
+    want = native.AhoCorasick(pats, 4).scan(text)
+    a = pfac.pfac_build(pats, 4)
+    t = _dev(text)
+    combos = [(s, d, k) for s in (10, 12, 14, 16) for d in range(1, 9) for k in range(d, 17)]
+    for i in rng.choice(len(combos), size=24, replace=False):
+        s, d, k = combos[int(i)]
+        pfac.pfac_set_tuning(a, span_log2=s, root_depth=d, filter_k=k)
+        got = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+        assert np.array_equal(got, want), (s, d, k)
+
+
+def test_autotuner_keeps_results_and_reports_its_choice():
+    w = W.packets_256(n_packets=8192, n_patterns=4000, plant_every=4)
+    a = pfac.pfac_build(w.patterns, w.alphabet)
+    want = native.AhoCorasick(w.patterns, w.alphabet).scan_packets(w.data, w.offsets)
+    d = _dev(w.data)
+    o = _dev(w.offsets.view(np.int64), torch.int64)
+    t = pfac.pfac_tune(a, d, o, reps=3)
+    assert t["algo"] == "tiled" and 10 <= t["span_log2"] <= 16 and t["ms"] > 0
+    assert pfac.pfac_get_tuning(a) == {k: v for k, v in t.items() if k != "ms"}
+    got = pfac.keys_to_numpy(pfac.pfac_scan_batch(a, d, o))
+    assert np.array_equal(got, want)
+
+
+def test_graph_outlives_a_change_of_tuning():
+    rng = np.random.default_rng(13)
+    pats, text = _case(rng, 256, 300, 1 << 19, 4, 30)
+    ac = native.AhoCorasick(pats, 256)
+    a = pfac.pfac_build(pats, 256)
+    t = _dev(text)
+    keys = torch.zeros(1 << 16, dtype=torch.int64, device=DEV)
+    count = torch.zeros(1, dtype=torch.int64, device=DEV)
+    sizes = torch.tensor([len(text), 0], dtype=torch.int64, device=DEV)
+    s = torch.cuda.Stream()
+    g = pfac.pfac_graph_create(a, t, None, keys, count, sizes, s)
+    want = ac.scan(text)
+    for d, k, span in [(1, 3, 12), (2, 2, 16), (2, 4, 10)]:
+        pfac.pfac_set_tuning(a, root_depth=d, filter_k=k, span_log2=span)
+        g.launch(s)
+        s.synchronize()
+        c = int(count.item())
+        assert c == len(want) and np.array_equal(pfac.keys_to_numpy(keys[:c]), want), (d, k, span)
+        assert np.array_equal(pfac.keys_to_numpy(pfac.pfac_scan(a, t)), want)
+    g.close()
