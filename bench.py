@@ -33,6 +33,9 @@ WORKLOADS = {
     "uniform_256": "1 MiB uniform text, 100 patterns (4-16 bytes), alphabet 256, 1,000 plants",
     "dna_4": ("1 GiB order-2 Markov DNA text (codes 0-3), 10,000 patterns (8-32), "
               "alphabet 4, one plant per MiB"),
+    "serving_256": ("open-loop Poisson requests at 40 Gbit/s offered for 2 s, 32 packets per "
+                    "request (64/512/1500/9000 B uniform, random bytes), 50,000 patterns "
+                    "(log-normal, median 16, 4-256), alphabet 256"),
     "packets_256": ("65,536 packets (64/576/1500 B at 40/20/40 %, 80 % printable), 20,000 "
                     "patterns (4-128 B, heads from a depth-6 branching-3 tree), alphabet 256"),
 }
@@ -214,6 +217,81 @@ def bench_packets(args, w):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args):
+    """Serving loop under an open-loop Poisson stream: requests are submitted at their
+    scheduled arrival times (latency counts from the schedule, so a late client shows as
+    latency), results are drained by a second thread, and the server's own statistics
+    give per-packet p50/p99 latency and the achieved rate."""
+    import threading
+
+    import paper_1704_02272_amd.pfac as pfac
+    from paper_1704_02272_amd import workloads as W
+
+    w = W.serving_256(duration_s=args.serve_seconds, contiguous=True, plant_every=args.plant_every)
+    a = pfac.pfac_build(w.patterns, w.alphabet)
+    srv = pfac.pfac_server_create(a, slots=args.slots, max_batch_bytes=args.batch_mib << 20)
+    cfg = srv.config()
+    ptrs = [(r.data.ctypes.data, r.offsets.ctypes.data, int(r.offsets[-1])) for r in w.requests]
+    arr_ns = [int(r.arrival_s * 1e9) for r in w.requests]
+    # warm-up: a few requests through every slot
+    for i in range(min(64, len(ptrs))):
+        srv.submit_raw(ptrs[i][0], ptrs[i][1], w.packets_per_request)
+    seen = 0
+    while seen < min(64, len(ptrs)):
+        seen += len(srv.poll(timeout_us=100000, with_keys=False))
+    srv.stats(reset=True)
+    done = {"n": 0, "matches": 0, "bad": 0}
+    n_total = len(ptrs)
+    stop = threading.Event()
+
+    def drain():
+        while done["n"] < n_total and not stop.is_set():
+            for r in srv.poll(timeout_us=50000, with_keys=False):
+                done["n"] += 1
+                done["matches"] += r["n_matches"]
+                done["bad"] += r["status"] != 0
+
+    th = threading.Thread(target=drain, daemon=True)
+    th.start()
+    t0 = time.monotonic_ns() + 20_000_000
+    busy = 0
+    i = 0
+    while i < n_total:
+        now = time.monotonic_ns()
+        while i < n_total and t0 + arr_ns[i] <= now:
+            rc = srv.submit_raw(ptrs[i][0], ptrs[i][1], w.packets_per_request, t0 + arr_ns[i])
+            if rc == pfac.PFAC_EBUSY:
+                busy += 1
+            elif rc:
+                raise pfac.PfacError(rc, "pfac_server_submit")
+            i += 1
+        if i < n_total:
+            wait = (t0 + arr_ns[i] - time.monotonic_ns()) / 1e9
+            if wait > 2e-4:
+                time.sleep(wait - 1e-4)
+    th.join(timeout=120)
+    stop.set()
+    st = srv.stats()
+    srv.close()
+    offered = 8.0 * sum(p[2] for p in ptrs) / (arr_ns[-1] / 1e9) / 1e9
+    out = {
+        "metric": METRIC, "value": round(st["bytes_per_s"] * 8 / 1e9, 3), "unit": "Gbit/s", "n_gpus": 1,
+        "steps": n_total, "warmup": 64, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded numpy generator; see DESIGN.md input recipe)",
+        "config": {"workload": "serving_256", "description": WORKLOADS["serving_256"],
+                   "requests": n_total, "patterns": len(w.patterns), "server": cfg,
+                   "plant_every": args.plant_every},
+        "serving": {"offered_gbit_s": round(offered, 3), "achieved_gbit_s": round(st["bytes_per_s"] * 8 / 1e9, 3),
+                    "p50_us": round(st["p50_ns"] / 1e3, 1), "p99_us": round(st["p99_ns"] / 1e3, 1),
+                    "max_us": round(st["max_ns"] / 1e3, 1), "requests_done": done["n"],
+                    "rejected_busy": busy, "failed": done["bad"], "batches": st["batches"],
+                    "mean_batch_kib": round(st["mean_batch_bytes"] / 1024, 1), "matches": done["matches"]},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +303,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="packets: skip the autotuner")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="serving: seconds of offered load")
+    ap.add_argument("--slots", type=int, default=4, help="serving: batch slots")
+    ap.add_argument("--batch-mib", type=int, default=8, help="serving: MiB per batch")
+    ap.add_argument("--plant-every", type=int, default=0, help="serving: planted variant")
     ap.add_argument("--baseline-steps", type=int, default=3,
                     help="packets: timed passes of the per-packet baseline")
     ap.add_argument("--mode", default="scan", choices=["scan", "copy"],
@@ -243,6 +325,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "serving_256":
+        bench_serving(args)
+        return
     w = make_workload(args.workload)
     if args.workload == "packets_256":
         bench_packets(args, w)

@@ -52,6 +52,7 @@ extern "C" {
 #define PFAC_EFORMAT (-9)        /* serialized automaton is malformed or truncated      */
 #define PFAC_ETIMEOUT (-10)      /* a device-side bounded wait expired (internal error) */
 #define PFAC_EINTERNAL (-11)     /* an internal consistency check failed               */
+#define PFAC_EBUSY (-12)         /* a server's waiting queue is full; submit again later */
 
 /* Human-readable name of a status code (static storage, never NULL). */
 PFAC_API const char *pfac_strerror(int status);
@@ -226,6 +227,90 @@ PFAC_API int pfac_graph_launch(pfac_graph *g, void *stream);
 
 /* Free the graph and its scratch. NULL is a no-op. */
 PFAC_API void pfac_graph_destroy(pfac_graph *g);
+
+/* ------------------------------------------------------------------- serving loop
+ * A server keeps the automaton resident on the current device and scans packet requests
+ * as they arrive (continuous batching). Requests wait in a FIFO; a worker thread owns
+ * `slots` batch slots, each with its own device buffers, stream and captured scan graph.
+ * Whenever a slot is free, the worker packs every waiting request that fits
+ * (max_batch_bytes / max_batch_packets) into one batch and launches it at once, so
+ * requests that arrive while other batches run on the GPU are admitted as slots free up,
+ * and the batches of different slots overlap on the device. Each packet is scanned as
+ * its own text (as in pfac_scan_batch), so a request's result does not depend on what
+ * it was batched with.
+ *
+ * Admission by device memory: at creation the server computes the device memory one
+ * slot needs (batch buffers, key buffer, scan scratch) and keeps only as many slots as
+ * device_memory_budget holds (0 = a quarter of the device's free memory); fewer than
+ * one slot is PFAC_ENOMEM. Waiting requests are bounded by max_pending_bytes: a submit
+ * beyond it returns PFAC_EBUSY. Fields left 0 take the defaults shown. */
+typedef struct {
+    uint32_t slots;               /* batches in flight at once (4)                       */
+    uint32_t max_batch_packets;   /* packets per batch, and per request (16,384)         */
+    uint64_t max_batch_bytes;     /* bytes per batch, and per request (8 MiB; < 2^32)    */
+    uint64_t key_capacity;        /* keys a slot returns without a rescan (65,536)       */
+    uint64_t max_pending_bytes;   /* bytes allowed to wait for a slot (1 GiB)            */
+    uint64_t device_memory_budget;/* device bytes all slots may hold (0 = free / 4)      */
+    uint32_t reserved[4];
+} pfac_server_config;
+
+/* One finished request. keys: (offset of the match start within the request's bytes
+ * << 32) | pattern_id, sorted; map a start to its packet with the request's offsets.
+ * Times are CLOCK_MONOTONIC nanoseconds: arrival (as submitted), launch of its batch,
+ * completion seen by the server. status != PFAC_OK means the request was not scanned
+ * (keys NULL). Free keys with pfac_result_free. */
+typedef struct {
+    uint64_t ticket;
+    int32_t status;
+    uint32_t n_pkts;
+    uint64_t n_bytes;
+    uint64_t n_matches;
+    uint64_t *keys;
+    uint64_t arrival_ns, launch_ns, done_ns;
+} pfac_result;
+
+typedef struct {
+    uint64_t requests, packets, bytes, matches; /* completed since the last reset          */
+    uint64_t batches, rejected, pending_requests;
+    uint32_t slots, reserved0;
+    double bytes_per_s;       /* completed bytes / (last completion - first arrival)        */
+    double mean_batch_bytes;
+    uint64_t p50_ns, p99_ns, max_ns; /* per-packet latency: completion - arrival, each
+                                        request counted once per packet                 */
+} pfac_server_stats_t;
+
+typedef struct pfac_server pfac_server;
+
+/* Create a server for automaton a (which must have patterns and outlive the server) on
+ * the current device; cfg may be NULL. Errors: PFAC_EINVAL, PFAC_ENODEVICE, PFAC_ENOMEM
+ * (budget below one slot, or allocation), PFAC_EHIP. */
+PFAC_API int pfac_server_create(pfac_automaton *a, const pfac_server_config *cfg, pfac_server **out);
+
+/* The configuration in force (defaults filled in, slots as admitted). */
+PFAC_API int pfac_server_config_get(const pfac_server *s, pfac_server_config *out);
+
+/* Submit one request: n_pkts packets, packet i = h_bytes[h_offsets[i] .. h_offsets[i+1])
+ * (host memory, copied before return; h_offsets[0] = 0, non-decreasing). arrival_ns: its
+ * arrival time on CLOCK_MONOTONIC (0 = now). *ticket identifies its result. Thread safe.
+ * Errors: PFAC_EINVAL, PFAC_ETOO_LARGE (over a batch's limits), PFAC_EBUSY (queue full),
+ * PFAC_ENOMEM, or the error that stopped the server. */
+PFAC_API int pfac_server_submit(pfac_server *s, const uint8_t *h_bytes, const uint64_t *h_offsets,
+                                uint32_t n_pkts, uint64_t arrival_ns, uint64_t *ticket);
+
+/* Move up to max_results finished requests (completion order) into res; waits up to
+ * timeout_us microseconds when none is ready. *n_out = number returned. */
+PFAC_API int pfac_server_poll(pfac_server *s, pfac_result *res, uint32_t max_results, uint32_t *n_out,
+                              uint32_t timeout_us);
+
+/* Free a result's keys. */
+PFAC_API void pfac_result_free(pfac_result *r);
+
+/* Counters and latency percentiles; reset != 0 clears them after reading. */
+PFAC_API int pfac_server_stats(pfac_server *s, pfac_server_stats_t *st, int reset);
+
+/* Finish every submitted request, stop the worker and free the server. Results not yet
+ * polled are freed. NULL is a no-op. */
+PFAC_API void pfac_server_destroy(pfac_server *s);
 
 /* ------------------------------------------------------------------- tuning
  * Launch choices of an automaton's scans. None of them changes any result (positions

@@ -22,6 +22,7 @@ extern "C" const char *pfac_strerror(int status) {
         case PFAC_EFORMAT: return "malformed serialized automaton";
         case PFAC_ETIMEOUT: return "device-side wait timed out";
         case PFAC_EINTERNAL: return "internal consistency check failed";
+        case PFAC_EBUSY: return "server queue is full";
         default: return "unknown status";
     }
 }

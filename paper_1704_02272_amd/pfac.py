@@ -31,6 +31,7 @@ PFAC_ENODEVICE = -8
 PFAC_EFORMAT = -9
 PFAC_ETIMEOUT = -10
 PFAC_EINTERNAL = -11
+PFAC_EBUSY = -12
 
 _lib = None
 
@@ -56,6 +57,26 @@ class Match(C.Structure):
 
 class Matches(C.Structure):
     _fields_ = [("matches", C.POINTER(Match)), ("count", C.c_uint64)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("max_batch_packets", C.c_uint32), ("max_batch_bytes", C.c_uint64),
+                ("key_capacity", C.c_uint64), ("max_pending_bytes", C.c_uint64),
+                ("device_memory_budget", C.c_uint64), ("reserved", C.c_uint32 * 4)]
+
+
+class Result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("n_pkts", C.c_uint32),
+                ("n_bytes", C.c_uint64), ("n_matches", C.c_uint64), ("keys", C.POINTER(C.c_uint64)),
+                ("arrival_ns", C.c_uint64), ("launch_ns", C.c_uint64), ("done_ns", C.c_uint64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("requests", "packets", "bytes", "matches", "batches", "rejected",
+                                          "pending_requests")] + [
+        ("slots", C.c_uint32), ("reserved0", C.c_uint32), ("bytes_per_s", C.c_double),
+        ("mean_batch_bytes", C.c_double), ("p50_ns", C.c_uint64), ("p99_ns", C.c_uint64),
+        ("max_ns", C.c_uint64)]
 
 
 MATCH_DTYPE = np.dtype([("start", np.uint64), ("pattern_id", np.uint32), ("reserved", np.uint32)])
@@ -103,6 +124,13 @@ def lib():
             "pfac_graph_destroy": (None, [VP]),
             "pfac_scan_host": (C.c_int, [VP, VP, C.c_uint64, C.c_uint64, C.POINTER(Matches)]),
             "pfac_matches_free": (None, [C.POINTER(Matches)]),
+            "pfac_server_create": (C.c_int, [VP, C.POINTER(ServerConfig), C.POINTER(VP)]),
+            "pfac_server_config_get": (C.c_int, [VP, C.POINTER(ServerConfig)]),
+            "pfac_server_submit": (C.c_int, [VP, VP, VP, C.c_uint32, C.c_uint64, P64]),
+            "pfac_server_poll": (C.c_int, [VP, C.POINTER(Result), C.c_uint32, P32, C.c_uint32]),
+            "pfac_result_free": (None, [C.POINTER(Result)]),
+            "pfac_server_stats": (C.c_int, [VP, C.POINTER(ServerStats), C.c_int]),
+            "pfac_server_destroy": (None, [VP]),
             "pfac_set_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
             "pfac_get_tuning": (C.c_int, [VP, C.POINTER(Tuning)]),
             "pfac_tune": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint32, C.c_uint32, VP,
@@ -392,6 +420,83 @@ def pfac_scan_host(a: Automaton, text, chunk_bytes: int = 0) -> np.ndarray:
         return np.frombuffer(buf, dtype=MATCH_DTYPE).copy()
     finally:
         lib().pfac_matches_free(C.byref(m))
+
+
+class Server:
+    """Owns a ``pfac_server*`` (the serving loop; see ``pfac_server_create``)."""
+
+    def __init__(self, handle, automaton):
+        self.handle = handle
+        self._a = automaton  # the automaton must outlive the server
+        self._buf = (Result * 1024)()
+
+    def config(self) -> dict:
+        c = ServerConfig()
+        _check(lib().pfac_server_config_get(self.handle, C.byref(c)), "pfac_server_config_get")
+        return {n: getattr(c, n) for n, _ in ServerConfig._fields_ if n != "reserved"}
+
+    def submit(self, data: np.ndarray, offsets: np.ndarray, arrival_ns: int = 0) -> int:
+        """Submit one request (host numpy arrays: uint8 bytes, uint64 packet offsets)."""
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        t = C.c_uint64(0)
+        rc = lib().pfac_server_submit(self.handle, C.c_void_p(data.ctypes.data if data.size else 0),
+                                      C.c_void_p(offsets.ctypes.data), len(offsets) - 1, arrival_ns,
+                                      C.byref(t))
+        _check(rc, "pfac_server_submit")
+        return t.value
+
+    def submit_raw(self, data_ptr: int, offsets_ptr: int, n_pkts: int, arrival_ns: int = 0) -> int:
+        """Submit from raw host pointers (no conversion; returns the status, ticket in .last)."""
+        t = C.c_uint64(0)
+        rc = lib().pfac_server_submit(self.handle, C.c_void_p(data_ptr), C.c_void_p(offsets_ptr), n_pkts,
+                                      arrival_ns, C.byref(t))
+        self.last = t.value
+        return rc
+
+    def poll(self, timeout_us: int = 0, with_keys: bool = True) -> list:
+        """Finished requests: dicts with ticket, status, n_pkts, n_bytes, n_matches, keys
+        (uint64 numpy array), arrival_ns, launch_ns, done_ns."""
+        n = C.c_uint32(0)
+        _check(lib().pfac_server_poll(self.handle, self._buf, len(self._buf), C.byref(n), timeout_us),
+               "pfac_server_poll")
+        out = []
+        for i in range(n.value):
+            r = self._buf[i]
+            keys = None
+            if with_keys:
+                keys = (np.ctypeslib.as_array(r.keys, shape=(int(r.n_matches),)).copy()
+                        if r.n_matches else np.zeros(0, dtype=np.uint64))
+            out.append({"ticket": r.ticket, "status": r.status, "n_pkts": r.n_pkts, "n_bytes": r.n_bytes,
+                        "n_matches": r.n_matches, "keys": keys, "arrival_ns": r.arrival_ns,
+                        "launch_ns": r.launch_ns, "done_ns": r.done_ns})
+            lib().pfac_result_free(C.byref(r))
+        return out
+
+    def stats(self, reset: bool = False) -> dict:
+        st = ServerStats()
+        _check(lib().pfac_server_stats(self.handle, C.byref(st), int(reset)), "pfac_server_stats")
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_ if n != "reserved0"}
+
+    def close(self):
+        if self.handle:
+            lib().pfac_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pfac_server_create(a: Automaton, **cfg) -> Server:
+    c = ServerConfig()
+    for k, v in cfg.items():
+        setattr(c, k, v)
+    h = C.c_void_p()
+    _check(lib().pfac_server_create(a.handle, C.byref(c), C.byref(h)), "pfac_server_create")
+    return Server(h.value, a)
 
 
 def keys_to_numpy(keys) -> np.ndarray:

@@ -300,11 +300,16 @@ SERVING_SIZES = np.array([64, 512, 1500, 9000])
 def serving_256(seed: int = 5, n_patterns: int = 50000, offered_gbit_s: float = 40.0,
                 duration_s: float = 2.0, packets_per_request: int = 32,
                 pool_bytes: int = 1 << 30, plant_every: int = 0,
-                max_requests: int | None = None) -> ServingWorkload:
+                max_requests: int | None = None, contiguous: bool = False) -> ServingWorkload:
     """Open-loop Poisson request stream at ``offered_gbit_s``. Each request is a batch
     of ``packets_per_request`` packets with sizes uniform over {64, 512, 1500, 9000};
     payloads are slices of a seeded uniform random pool (optionally with one planted
-    whole pattern per packet with probability 1/``plant_every``)."""
+    whole pattern per packet with probability 1/``plant_every``).
+
+    ``contiguous=True`` makes each request one slice of the pool, held as a view (no
+    copy), with plants written into the pool itself: a 2 s stream at 40 Gbit/s is then
+    10 GB of requests over a 1 GiB pool without 10 GB of copies. Later plants may land
+    in earlier requests' slices; the bytes a request finally views are its payload."""
     rng = np.random.default_rng(seed)
     lens = lognormal_lengths(rng, n_patterns, 16.0, 0.5, 4, 256)
     pats = [rng.integers(0, 256, size=int(L), dtype=np.uint8).tobytes() for L in lens]
@@ -320,6 +325,28 @@ def serving_256(seed: int = 5, n_patterns: int = 50000, offered_gbit_s: float = 
     order = np.argsort(lens, kind="stable")
     sorted_lens = lens[order]
     reqs = []
+    if contiguous:
+        sizes = SERVING_SIZES[rng.integers(0, 4, size=(n_req, packets_per_request))]
+        offs = np.zeros((n_req, packets_per_request + 1), dtype=np.uint64)
+        np.cumsum(sizes, axis=1, out=offs[:, 1:])
+        starts = rng.integers(0, pool_bytes - offs[:, -1].astype(np.int64) + 1)
+        for r in range(n_req):
+            a = int(starts[r])
+            data = pool[a:a + int(offs[r, -1])]
+            if plant_every:
+                for i in np.nonzero(rng.integers(0, plant_every, size=packets_per_request) == 0)[0]:
+                    s = int(sizes[r, i])
+                    fit = int(np.searchsorted(sorted_lens, s, side="right"))
+                    if fit:
+                        p = pats[int(order[int(rng.integers(0, fit))])]
+                        o = int(offs[r, i]) + int(rng.integers(0, s - len(p) + 1))
+                        data[o:o + len(p)] = np.frombuffer(p, dtype=np.uint8)
+            reqs.append(Request(float(arrivals[r]), data, offs[r]))
+        name = "serving_256" + ("_planted" if plant_every else "")
+        return ServingWorkload(name, 256, pats, seed, offered, packets_per_request, pool, reqs,
+                               "Poisson arrivals; 32 packets/request U{64,512,1500,9000}, each "
+                               "request one pool slice; patterns lognormal(ln 16, 0.5) clip "
+                               "4..256 x U{0..255}")
     for r in range(n_req):
         sizes = SERVING_SIZES[rng.integers(0, 4, size=packets_per_request)]
         offs = np.zeros(packets_per_request + 1, dtype=np.uint64)

@@ -186,3 +186,21 @@ def test_host_scan_argument_errors():
     assert L.pfac_scan_host(a.handle, None, 0, 0, C.byref(m)) == pfac.PFAC_OK and m.count == 0
     L.pfac_matches_free(C.byref(m))
     L.pfac_matches_free(None)
+
+
+def test_server_argument_errors():
+    L = pfac.lib()
+    h = C.c_void_p(7)
+    empty = pfac.pfac_build([], 256)
+    # no automaton, an automaton without patterns: rejected before any device work
+    assert L.pfac_server_create(None, None, C.byref(h)) == pfac.PFAC_EINVAL and h.value is None
+    assert L.pfac_server_create(empty.handle, None, C.byref(h)) == pfac.PFAC_EINVAL
+    t = C.c_uint64(0)
+    assert L.pfac_server_submit(None, None, None, 0, 0, C.byref(t)) == pfac.PFAC_EINVAL
+    n = C.c_uint32(5)
+    assert L.pfac_server_poll(None, None, 0, C.byref(n), 0) == pfac.PFAC_EINVAL
+    st = pfac.ServerStats()
+    assert L.pfac_server_stats(None, C.byref(st), 0) == pfac.PFAC_EINVAL
+    L.pfac_server_destroy(None)
+    L.pfac_result_free(None)
+    assert pfac.strerror(pfac.PFAC_EBUSY) == "server queue is full"

@@ -81,3 +81,15 @@ def test_serving_256_shape():
     for r in w.requests[:20]:
         sizes = np.diff(r.offsets)
         assert len(sizes) == 32 and set(np.unique(sizes)) <= {64, 512, 1500, 9000}
+
+
+def test_serving_256_contiguous_views_share_the_pool():
+    w = W.serving_256(n_patterns=500, pool_bytes=1 << 22, max_requests=200, plant_every=4, contiguous=True)
+    assert len(w.requests) == 200
+    for r in w.requests:
+        assert r.data.base is w.pool or r.data.base is w.pool.base
+        assert len(r.data) == int(r.offsets[-1])
+        assert set(np.unique(np.diff(r.offsets))) <= {64, 512, 1500, 9000}
+    # planted patterns exist in the pool
+    hits = sum(1 for p in w.patterns[:500] if bytes(p) in w.pool.tobytes())
+    assert hits > 0
