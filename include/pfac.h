@@ -321,9 +321,10 @@ PFAC_API void pfac_server_destroy(pfac_server *s);
  *               (persistent count kernel with the LDS prefilter and root image, then the
  *               placement kernel).
  *   grid        workgroups of the count kernel (0 = as many as are resident at once).
- *   span_log2   log2 of the bytes one wave scans as a unit (its chunk): 10..16, 0 = 14.
- *               Smaller spans spread small batches over more waves; each span costs
- *               2 KiB of per-stream scratch.
+ *   span_log2   log2 of the bytes one wave scans as a unit (its chunk): 10..16; 0 = per
+ *               scan, the longest span (4..64 KiB) that still gives every resident wave
+ *               one. Smaller spans spread small texts over more waves; a span keeps up to
+ *               max(256, span / 64) match records in per-stream scratch.
  *   root_depth  trie levels folded into the LDS root image (1..min(shortest pattern, 2),
  *               or ..8 for alphabets <= 4); 0 = the builder's choice.
  *   filter_k    symbols per LDS prefilter key (root_depth..min(longest pattern, 4), or ..16

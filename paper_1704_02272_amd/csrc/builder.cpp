@@ -135,6 +135,41 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
 
 }  // namespace
 
+// Path tails (see DevTable::tails), bottom-up over the breadth-first order: node q
+// qualifies when it has one child c and c is a leaf, or c is not terminal and qualifies.
+// The path's symbols are those of a pattern ending at its end node, from q's depth on.
+void build_tails(pfac_automaton *a) {
+    const uint32_t Q = a->n_nodes;
+    a->dev_tails.assign((size_t)Q * 4, 0);
+    if (a->pat_bytes.size() >= (1ull << 32)) return;  // offsets are 32-bit: no tails
+    auto term = [&](uint32_t q) { return a->out_first[q + 1] > a->out_first[q]; };
+    auto nchild = [&](uint32_t q) {
+        uint32_t c = 0;
+        for (uint32_t w = 0; w < a->nbw; w++) c += popc64(a->bitmap[(size_t)q * a->nbw + w]);
+        return c;
+    };
+    uint32_t d = (uint32_t)a->depth_start.size() - 1;
+    for (uint32_t q = Q; q-- > 0;) {
+        while (d > 0 && a->depth_start[d] > q) d--;  // depth of q
+        if (nchild(q) != 1) continue;
+        const uint32_t c = a->first_child[q];
+        uint32_t len = 0, leaf = 0;
+        if (a->first_child[c] == 0) {
+            len = 1;
+            leaf = c;
+        } else if (!term(c) && a->dev_tails[(size_t)c * 4 + 1]) {
+            len = 1 + a->dev_tails[(size_t)c * 4 + 1];
+            leaf = a->dev_tails[(size_t)c * 4 + 2];
+        } else {
+            continue;
+        }
+        const uint32_t j = a->out_ids[a->out_first[leaf]];
+        a->dev_tails[(size_t)q * 4 + 0] = (uint32_t)(a->pat_off[j] + d);
+        a->dev_tails[(size_t)q * 4 + 1] = len;
+        a->dev_tails[(size_t)q * 4 + 2] = leaf;
+    }
+}
+
 int rebuild_lds_image(pfac_automaton *a, uint32_t D, uint32_t K) {
     if (!a || a->n_pats == 0) return (D || K) ? PFAC_EINVAL : PFAC_OK;
     const bool pack2 = a->alphabet <= 4;
@@ -260,6 +295,11 @@ int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n
                 a->dev_nodes[q] = m;
             }
         }
+        a->pat_off.assign(n_pats + 1, 0);
+        for (uint32_t j = 0; j < n_pats; j++) a->pat_off[j + 1] = a->pat_off[j] + lens[j];
+        a->pat_bytes.resize(a->pat_off[n_pats]);
+        for (uint32_t j = 0; j < n_pats; j++) memcpy(a->pat_bytes.data() + a->pat_off[j], P[j], lens[j]);
+        build_tails(a);
         DevTable &t = a->shape;
         t = DevTable{};
         t.alphabet = alphabet;
@@ -268,10 +308,6 @@ int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n
         t.n_nodes = a->n_nodes;
         t.min_len = minl;
         t.max_len = maxl;
-        a->pat_off.assign(n_pats + 1, 0);
-        for (uint32_t j = 0; j < n_pats; j++) a->pat_off[j + 1] = a->pat_off[j] + lens[j];
-        a->pat_bytes.resize(a->pat_off[n_pats]);
-        for (uint32_t j = 0; j < n_pats; j++) memcpy(a->pat_bytes.data() + a->pat_off[j], P[j], lens[j]);
         build_lds_image(a, P, 0, 0);
         (void)total;
     } catch (const std::bad_alloc &) {

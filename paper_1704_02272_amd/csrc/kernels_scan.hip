@@ -23,7 +23,8 @@
 //    time, one per lane, mostly at the end of the span so walks seldom stall the stream
 //    of text loads. Walks read nodes and text through L2.
 //  * Per span the kernel stores the match count and one record per matching start
-//    (start, first terminal node, number of terminals), up to kHCap records.
+//    (start, first terminal node, number of terminals), up to span / 64 records (at
+//    least 256).
 //
 // Placement kernel (place_emit): blocks of kBlockSpans spans, taken by ticket. A block
 // sums its spans' counts, finds its output offset by decoupled look-back over earlier
@@ -108,21 +109,53 @@ struct Trie {
         }
     }
 
+    // Path tail of q: x = offset in tail_bytes, y = length (0: none), z = end node.
+    __device__ __forceinline__ uint4 tail(uint32_t q) const { return reinterpret_cast<const uint4 *>(t.tails)[q]; }
+
+    // Whether text[i .. i+len) spells tail_bytes[off .. off+len); 16 byte pairs per round
+    // of loads, all issued before any is compared.
+    __device__ __forceinline__ bool tail_equal(const uint8_t *__restrict__ text, uint64_t i, uint32_t off,
+                                               uint32_t len) const {
+        for (uint32_t o = 0; o < len; o += 16) {
+            uint32_t diff = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < 16; k++)
+                if (o + k < len) diff |= (uint32_t)text[i + o + k] ^ (uint32_t)t.tail_bytes[off + o + k];
+            if (diff) return false;
+        }
+        return true;
+    }
+
+    // One move of a walk at node q, text position i < end: along q's whole path tail when
+    // it has one, else one symbol by Eq. 1. False when the walk ends here.
+    __device__ __forceinline__ bool advance(uint32_t &q, uint64_t &i, uint4 tl, const uint8_t *__restrict__ text,
+                                            uint32_t c, uint64_t end) const {
+        if (tl.y) {
+            if (i + tl.y > end || !tail_equal(text, i, tl.x, tl.y)) return false;
+            q = tl.z;
+            i += tl.y;
+            return true;
+        }
+        const int64_t nq = child(q, c);
+        if (nq < 0) return false;
+        q = (uint32_t)nq;
+        i++;
+        return true;
+    }
+
     // Walk from node q at text position i (end exclusive): count ids of every terminal,
     // including q itself.
     __device__ WalkResult walk_from(uint32_t q, const uint8_t *__restrict__ text, uint64_t i, uint64_t end) const {
         WalkResult r{0, 0, 0};
         for (;;) {
+            const uint4 tl = tail(q);
             if (is_term(q)) {
                 r.cnt += ids(q);
                 r.term0 = r.nterm == 0 ? q : r.term0;
                 r.nterm++;
             }
             if (i >= end) break;
-            const int64_t nq = child(q, text[i]);
-            if (nq < 0) break;
-            q = (uint32_t)nq;
-            i++;
+            if (!advance(q, i, tl, text, text[i], end)) break;
         }
         return r;
     }
@@ -136,16 +169,14 @@ struct Trie {
         uint32_t q = 0, k = 0, nterm = 0;
         uint64_t i = s;
         for (;;) {
+            const uint4 tl = tail(q);
             if (is_term(q)) {
                 nterm++;
                 for (uint32_t x = t.out_first[q]; x < t.out_first[q + 1]; x++) keys[o + k++] = hi | t.out_ids[x];
                 if (k >= cnt) break;
             }
             if (i >= end) break;
-            const int64_t nq = child(q, text[i]);
-            if (nq < 0) break;
-            q = (uint32_t)nq;
-            i++;
+            if (!advance(q, i, tl, text, text[i], end)) break;
         }
         if (nterm > 1) {
             for (uint32_t a = 1; a < cnt; a++) {
@@ -193,6 +224,7 @@ struct RootWalk {
         WalkResult r{0, 0, 0};
         uint64_t i = s + D;
         for (;;) {
+            const uint4 tl = T.tail(q);
             if (T.is_term(q)) {
                 r.cnt += T.ids(q);
                 r.term0 = r.nterm == 0 ? q : r.term0;
@@ -201,10 +233,7 @@ struct RootWalk {
             if (i >= end) break;
             const uint32_t d = (uint32_t)(i - s);
             const uint32_t c = d < 8 ? (uint32_t)(w8 >> (8 * d)) & 0xffu : (uint32_t)text[i];
-            const int64_t nq = T.child(q, c);
-            if (nq < 0) break;
-            q = (uint32_t)nq;
-            i++;
+            if (!T.advance(q, i, tl, text, c, end)) break;
         }
         return r;
     }
@@ -221,6 +250,9 @@ __device__ __forceinline__ uint64_t packet_end(const uint64_t *__restrict__ offs
     }
     return offsets[lo + 1];
 }
+
+// 16 text bytes at an aligned address.
+__device__ __forceinline__ uint4 stream16(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
 
 // 16 bytes at p; bytes at or past `lim` read as zero (no load at all when p >= lim).
 // Vector load when the 16 bytes are whole and aligned.
@@ -263,6 +295,21 @@ __device__ __forceinline__ uint32_t probe(const uint32_t *img, uint32_t key, uin
     return __builtin_amdgcn_ubfe(w, key, 1);
 }
 
+// Second probe of a key that passed the first (see filter2_hash).
+__device__ __forceinline__ uint32_t probe2(const uint32_t *img, uint32_t key, uint32_t amask) {
+    const uint32_t h = filter2_hash(key);
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + (h & amask));
+    return (w >> (h >> 27)) & 1u;
+}
+
+// Four bytes starting at byte j (0..15) of the 20 bytes d0..d4 (little-endian words).
+__device__ __forceinline__ uint32_t bytes4_at(uint4 v, uint32_t d4, uint32_t j) {
+    const uint32_t qd = j >> 2;
+    const uint32_t lo = qd == 0 ? v.x : qd == 1 ? v.y : qd == 2 ? v.z : v.w;
+    const uint32_t hi = qd == 0 ? v.y : qd == 1 ? v.z : qd == 2 ? v.w : d4;
+    return __builtin_amdgcn_alignbyte(hi, lo, j & 3);
+}
+
 // One direct probe of the root bitmap: bit `key` of the bitmap at `root`.
 __device__ __forceinline__ uint32_t probe_root(const uint32_t *root, uint32_t key) {
     return __builtin_amdgcn_ubfe(root[key >> 5], key, 1);
@@ -284,22 +331,35 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
                 const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
                 mask |= probe(img, x, amask) << j;
             }
+            uint32_t rem = mask;
+            while (rem) {  // second probe of the few that passed
+                const uint32_t j = __builtin_ctz(rem);
+                rem &= rem - 1;
+                mask &= ~((probe2(img, bytes4_at(cur, next_d0, j), amask) ^ 1u) << j);
+            }
         } else if (t.filter_k) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
             const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
             const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : (1u << (8 * t.filter_k)) - 1u;
             const uint32_t *shrt = img + kLdsShort;
             const bool two = t.root_depth == 2, sh = t.has_short;
+            uint32_t ms = 0;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
-                uint32_t p = probe(img, x & kmask, amask);
+                mask |= probe(img, x & kmask, amask) << j;
                 if (sh) {
                     const uint32_t key = two ? (((x & 0xffu) << 8) | ((x >> 8) & 0xffu)) : (x & 0xffu);
-                    p |= probe_root(shrt, key);
+                    ms |= probe_root(shrt, key) << j;
                 }
-                mask |= p << j;
             }
+            uint32_t rem = mask & ~ms;
+            while (rem) {
+                const uint32_t j = __builtin_ctz(rem);
+                rem &= rem - 1;
+                mask &= ~((probe2(img, bytes4_at(cur, next_d0, j) & kmask, amask) ^ 1u) << j);
+            }
+            mask |= ms;
         } else {
             // root image as the filter: D-byte key, first byte most significant
             const uint32_t *root = img + kLdsRoot;
@@ -321,13 +381,21 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
             const uint32_t *shrt = img + kLdsShort;
             const uint32_t rsd = 32 - 2 * t.root_depth;
             const bool sh = t.has_short;
+            uint32_t ms = 0;
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
-                uint32_t p = probe(img, rs >= 32 ? top : top >> rs, amask);
-                if (sh) p |= probe_root(shrt, top >> rsd);
-                mask |= p << j;
+                mask |= probe(img, rs >= 32 ? top : top >> rs, amask) << j;
+                if (sh) ms |= probe_root(shrt, top >> rsd) << j;
             }
+            uint32_t rem = mask & ~ms;
+            while (rem) {
+                const uint32_t j = __builtin_ctz(rem);
+                rem &= rem - 1;
+                const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
+                mask &= ~((probe2(img, rs >= 32 ? top : top >> rs, amask) ^ 1u) << j);
+            }
+            mask |= ms;
         } else {
             const uint32_t *root = img + kLdsRoot;
 #pragma unroll
@@ -380,15 +448,16 @@ struct Scanner {
         const uint64_t hb = __ballot(r.cnt > 0);
         if (hb && S.ovf == kNone) {
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(hb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hb, 0u));
-            const bool store = r.cnt > 0 && S.nh + rank < kHCap;
+            const uint32_t hcap = 1u << so.rec_log2;
+            const bool store = r.cnt > 0 && S.nh + rank < hcap;
             if (store) {
                 const uint32_t nt = r.nterm < 0xffffu ? r.nterm : 0xffffu;
-                so.rec[(size_t)S.span * kHCap + S.nh + rank] = ((uint64_t)r.term0 << 32) | (nt << 16) | sl;
+                so.rec[((size_t)S.span << so.rec_log2) + S.nh + rank] = ((uint64_t)r.term0 << 32) | (nt << 16) | sl;
             }
             const uint64_t lost = __ballot(r.cnt > 0 && !store);
             if (lost) S.ovf = __builtin_amdgcn_readlane(sl, (int)__builtin_ctzll(lost));
             const uint32_t nh = S.nh + (uint32_t)__builtin_popcountll(hb);
-            S.nh = nh < kHCap ? nh : kHCap;
+            S.nh = nh < hcap ? nh : hcap;
         }
     }
 
@@ -416,15 +485,35 @@ struct Scanner {
         const uint32_t c = __builtin_popcount(m);
         const uint32_t inc = wave_incl_scan(c);
         const uint32_t tot = __builtin_amdgcn_readlane(inc, 63);
-        if (S.qlen + tot > kQCap) drain(S);  // now qlen < 64 and tot <= 1024
-        uint32_t at = S.qlen + inc - c;
-        while (m) {
-            const uint32_t j = __builtin_ctz(m);
-            m &= m - 1;
-            q[at++] = (uint16_t)(sl0 + j);
+        if (S.qlen + tot > kQCap) drain(S);  // now qlen < 64
+        if (S.qlen + tot <= kQCap) {
+            uint32_t at = S.qlen + inc - c;
+            while (m) {
+                const uint32_t j = __builtin_ctz(m);
+                m &= m - 1;
+                q[at++] = (uint16_t)(sl0 + j);
+            }
+            S.qlen += tot;
+            __builtin_amdgcn_wave_barrier();
+            return;
         }
-        S.qlen += tot;
-        __builtin_amdgcn_wave_barrier();
+        // more survivors in this step than the queue holds: queue them a window at a
+        // time (survivor k of the step is the k-th in position order), walking between
+        for (uint32_t done = 0; done < tot;) {
+            const uint32_t room = kQCap - S.qlen;
+            const uint32_t w = room < tot - done ? room : tot - done;
+            uint32_t mm = m, k = inc - c;
+            while (mm) {
+                const uint32_t j = __builtin_ctz(mm);
+                mm &= mm - 1;
+                if (k >= done && k < done + w) q[S.qlen + (k - done)] = (uint16_t)(sl0 + j);
+                k++;
+            }
+            __builtin_amdgcn_wave_barrier();
+            S.qlen += w;
+            done += w;
+            if (done < tot) drain(S);
+        }
     }
 
     // Survivor mask of the step at `step` (lane's 16 starts), cut to [S.a, top).
@@ -454,14 +543,14 @@ struct Scanner {
             // after the span are read for the last starts' windows.
             const uint64_t lastst = hiR - kStep;
             const uint4 tail = *reinterpret_cast<const uint4 *>(text + hiR);  // uniform address
-            uint4 cur = *reinterpret_cast<const uint4 *>(text + step + 16 * lane);
-            uint4 nx1 = *reinterpret_cast<const uint4 *>(text + (step + kStep < lastst ? step + kStep : lastst) + 16 * lane);
-            uint4 nx2 = *reinterpret_cast<const uint4 *>(text + (step + 2 * kStep < lastst ? step + 2 * kStep : lastst) + 16 * lane);
+            uint4 cur = stream16(text + step + 16 * lane);
+            uint4 nx1 = stream16(text + (step + kStep < lastst ? step + kStep : lastst) + 16 * lane);
+            uint4 nx2 = stream16(text + (step + 2 * kStep < lastst ? step + 2 * kStep : lastst) + 16 * lane);
             uint32_t pc = PACK2 ? pack2x16(cur) : 0u;
             const uint32_t ptail = PACK2 ? pack2x16(tail) : 0u;
             for (; step < hiR; step += kStep) {
                 const uint64_t a3 = step + 3 * kStep < lastst ? step + 3 * kStep : lastst;
-                const uint4 nx3 = *reinterpret_cast<const uint4 *>(text + a3 + 16 * lane);
+                const uint4 nx3 = stream16(text + a3 + 16 * lane);
                 const bool last = step == lastst;
                 const uint32_t dn = from_next_lane(cur.x);
                 const uint32_t d0n = last ? tail.x : __builtin_amdgcn_readfirstlane(nx1.x);
@@ -518,7 +607,7 @@ struct Scanner {
 
 // ------------------------------------------------------------------ count kernel
 template <int LAYOUT, bool PACK2, bool SEG>
-__global__ __launch_bounds__(kThreads) void scan_count(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
+__global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
                                                       const uint64_t *__restrict__ offsets, uint32_t n_packets,
                                                       SpanOut so, const uint64_t *__restrict__ sizes,
                                                       uint32_t span_log2) {
@@ -569,6 +658,8 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                                                            uint64_t *__restrict__ d_count, SpanOut so, TileState ts,
                                                            const uint64_t *__restrict__ sizes, uint32_t span_log2) {
     __shared__ uint64_t span_off[kBlockSpans];
+    __shared__ uint32_t span_nh[kBlockSpans];
+    __shared__ uint32_t span_cls[kBlockSpans];  // 0: no match, 1: one lane writes it, 2: a wave does
     __shared__ uint32_t sh[4];
     if (sizes) {
         n = sizes[0] < n ? sizes[0] : n;
@@ -597,7 +688,11 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
         if (wave == 0) {
             // the block's span counts, their prefix, and the block's place by look-back
             const uint32_t sp = blk * kBlockSpans + lane;
-            const uint64_t c = sp < n_spans ? so.cnt[sp] : 0;
+            const bool in = sp < n_spans;
+            const uint64_t c = in ? so.cnt[sp] : 0;
+            const uint32_t nh = in ? so.nh[sp] : 0, ovf = in ? so.ovf[sp] : kNone;
+            span_nh[lane] = nh;
+            span_cls[lane] = c == 0 ? 0u : (ovf == kNone && nh <= kFastRecs) ? 1u : 2u;
             uint64_t inc = c;
 #pragma unroll
             for (int d = 1; d < 64; d <<= 1) {
@@ -653,17 +748,47 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             span_off[lane] = excl + inc - c;
         }
         __syncthreads();
-        // each wave writes the keys of every kPlaceWaves-th span of the block
-        for (uint32_t i = wave; i < kBlockSpans; i += kPlaceWaves) {
+        if (wave == 0) {
+            // spans with a few records and no overflow: one lane each, all records'
+            // loads in flight at once
+            if (span_cls[lane] == 1) {
+                const uint32_t sp = blk * kBlockSpans + lane;
+                const uint64_t a = (uint64_t)sp << span_log2;
+                const uint32_t nh = span_nh[lane];
+                uint64_t o = span_off[lane];
+                uint64_t rec[kFastRecs];
+#pragma unroll
+                for (uint32_t k = 0; k < kFastRecs; k++) rec[k] = k < nh ? so.rec[((size_t)sp << so.rec_log2) + k] : 0;
+#pragma unroll
+                for (uint32_t k = 0; k < kFastRecs; k++) {
+                    if (k >= nh) break;
+                    const uint64_t s = a + (rec[k] & 0xffffu);
+                    const uint32_t nterm = (uint32_t)(rec[k] >> 16) & 0xffffu, q0 = (uint32_t)(rec[k] >> 32);
+                    if (nterm == 1) {
+                        const uint32_t f = t.out_first[q0], e = t.out_first[q0 + 1];
+                        if (o + (e - f) <= cap)
+                            for (uint32_t x = f; x < e; x++) keys[o + (x - f)] = (s << 32) | t.out_ids[x];
+                        o += e - f;
+                    } else {
+                        const uint64_t end = end_of(s);
+                        const uint32_t c = T.walk_from(0, text, s, end).cnt;
+                        if (c && o + c <= cap) T.emit_walk(text, s, end, keys, o, c);
+                        o += c;
+                    }
+                }
+            }
+        }
+        // the other spans: waves 1.. take every (kPlaceWaves - 1)-th
+        for (uint32_t i = wave - 1; wave > 0 && i < kBlockSpans; i += kPlaceWaves - 1) {
             const uint32_t sp = blk * kBlockSpans + i;
-            if (sp >= n_spans || so.cnt[sp] == 0) continue;
+            if (span_cls[i] != 2) continue;
             uint64_t run = span_off[i];
             const uint64_t a = (uint64_t)sp << span_log2;
             const uint64_t b = a + span_len < n ? a + span_len : n;
             const uint32_t nh = so.nh[sp], ovf = so.ovf[sp];
             for (uint32_t h0 = 0; h0 < nh; h0 += 64) {
                 const bool on = h0 + lane < nh;
-                const uint64_t rec = on ? so.rec[(size_t)sp * kHCap + h0 + lane] : 0;
+                const uint64_t rec = on ? so.rec[((size_t)sp << so.rec_log2) + h0 + lane] : 0;
                 const uint64_t s = a + (rec & 0xffffu);
                 const uint32_t nterm = (uint32_t)(rec >> 16) & 0xffffu, q0 = (uint32_t)(rec >> 32);
                 const uint64_t end = on ? end_of(s) : 0;
@@ -766,8 +891,10 @@ int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_
     uint64_t gp = (uint64_t)cus * (uint32_t)per_cu_p;
     if (gp > n_blocks) gp = n_blocks;
     if (gp == 0) gp = 1;
-    kc<<<(uint32_t)gc, kThreads, 0, s>>>(t, text, n, offsets, n_packets, so, sizes, span_log2);
-    kp<<<(uint32_t)gp, kPlaceThreads, 0, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes,
+    SpanOut o = so;
+    o.rec_log2 = rec_cap_log2(span_log2);
+    kc<<<(uint32_t)gc, kThreads, 0, s>>>(t, text, n, offsets, n_packets, o, sizes, span_log2);
+    kp<<<(uint32_t)gp, kPlaceThreads, 0, s>>>(t, text, n, offsets, n_packets, keys, cap, d_count, o, ts, sizes,
                                                span_log2);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

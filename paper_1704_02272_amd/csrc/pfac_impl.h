@@ -48,6 +48,12 @@ struct DevTable {
     const uint32_t *out_first;  // n_nodes + 1: ids of q at out_ids[out_first[q] .. [q+1])
     const uint32_t *out_ids;
     const uint32_t *lds_image;  // see above
+    // Path tails: tails[4q .. 4q+3] = {byte offset in tail_bytes, length, end node, 0}
+    // when everything below q is one path whose only terminal is its end (length > 0),
+    // else zeros. A walk at such a node compares the text with the path's symbols at
+    // once instead of stepping node by node; the result is the same.
+    const uint32_t *tails;
+    const uint8_t *tail_bytes;
     uint32_t alphabet;
     uint32_t layout;            // Layout
     uint32_t nw_log2;           // WIDE: log2(NW)
@@ -76,16 +82,26 @@ __host__ __device__ inline uint32_t filter_byte_offset(uint32_t key, uint32_t lo
     const uint32_t hi = (uint32_t)(((uint64_t)key * kFilterMul) >> 32);
     return hi & (((1u << (log2_bits - 5)) - 1u) << 2);
 }
+// Second hash of the same key (a two-probe Bloom filter): word from the high half of
+// key * kFilterMul2 the same way, bit = its top five bits. A key is present only if both
+// bits are set; the scan tests the second bit only for starts that passed the first.
+constexpr uint32_t kFilterMul2 = 0x85EBCA6Bu;  // odd multiplier (MurmurHash3 finalizer)
+__host__ __device__ inline uint32_t filter2_hash(uint32_t key) {
+    return (uint32_t)(((uint64_t)key * kFilterMul2) >> 32);
+}
 inline void filter_insert(uint32_t *F, uint32_t key, uint32_t log2_bits) {
     F[filter_byte_offset(key, log2_bits) >> 2] |= 1u << (key & 31);
+    const uint32_t h2 = filter2_hash(key);
+    F[(h2 & (((1u << (log2_bits - 5)) - 1u) << 2)) >> 2] |= 1u << (h2 >> 27);
 }
 
 struct Workspace;  // per (device, stream) scratch, defined in the runtime
 
 struct DeviceCopy {
     int device = -1;
+    uint32_t cus = 256;  // compute units of the device
     void *nodes = nullptr, *bm = nullptr, *out_first = nullptr, *out_ids = nullptr,
-         *lds_image = nullptr;
+         *lds_image = nullptr, *tails = nullptr, *tail_bytes = nullptr;
     DevTable view{};
     std::map<void *, Workspace *> workspaces;  // keyed by stream
     // LDS images replaced by a change of tuning. Queued scans and captured graphs may
@@ -100,7 +116,7 @@ struct pfac_automaton {
     uint32_t min_len = 0, max_len = 0;
     uint32_t layout = 0, nw = 0;  // nw: 64-bit bitmap words per node (WIDE)
     uint32_t algo = 0, grid = 0;  // tuning: kernel choice, persistent grid (0 = auto)
-    uint32_t span_log2 = 14;      // tuning: log2 of the count kernel's span length
+    uint32_t span_log2 = 0;       // tuning: log2 of the count kernel's span length (0 = by text size)
     uint32_t req_depth = 0, req_k = 0;  // tuning: requested root depth / filter key (0 = builder's)
     // The patterns as given (CSR), kept to rebuild the LDS image when tuning asks.
     std::vector<uint8_t> pat_bytes;
@@ -115,6 +131,7 @@ struct pfac_automaton {
     // Device images.
     std::vector<uint64_t> dev_nodes, dev_bm;
     std::vector<uint32_t> lds_image;
+    std::vector<uint32_t> dev_tails;  // 4 per node, see DevTable::tails
     pfac::DevTable shape{};  // pointer fields null; filled per device copy
     std::vector<pfac::DeviceCopy *> copies;
     std::mutex mu;

@@ -16,6 +16,7 @@ struct Workspace {
     uint64_t cap_blocks = 0;  // plain scan: per-block counts and offsets
     uint64_t *block_counts = nullptr, *block_offsets = nullptr;
     uint64_t cap_spans = 0;   // tiled scan: per-span results
+    uint64_t cap_recs = 0;    // tiled scan: match records (all spans)
     SpanOut so{};
     uint64_t cap_tiles = 0;   // tiled scan: look-back words (one per placement block)
     TileState ts{};
@@ -59,6 +60,7 @@ void free_tiles(Workspace *w) {
     hipFree(w->so.rec);
     w->so = SpanOut{};
     w->cap_spans = 0;
+    w->cap_recs = 0;
 }
 
 __global__ void clear_tiles_kernel(uint64_t *word, uint64_t n, uint32_t *ctrl) {
@@ -93,6 +95,8 @@ void free_copy(DeviceCopy *c) {
     hipFree(c->out_first);
     hipFree(c->out_ids);
     hipFree(c->lds_image);
+    hipFree(c->tails);
+    hipFree(c->tail_bytes);
     for (void *p : c->retired) hipFree(p);
     hipSetDevice(prev);
     delete c;
@@ -124,11 +128,16 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     DeviceCopy *c = new (std::nothrow) DeviceCopy();
     if (!c) return PFAC_ENOMEM;
     c->device = dev;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        c->cus = (uint32_t)cus;
     rc = upload_vec(a->dev_nodes, &c->nodes);
     if (!rc && a->layout == LAYOUT_WIDE) rc = upload_vec(a->dev_bm, &c->bm);
     if (!rc) rc = upload_vec(a->out_first, &c->out_first);
     if (!rc) rc = upload_vec(a->out_ids, &c->out_ids);
     if (!rc) rc = upload_vec(a->lds_image, &c->lds_image);
+    if (!rc) rc = upload_vec(a->dev_tails, &c->tails);
+    if (!rc) rc = upload_vec(a->pat_bytes, &c->tail_bytes);
     if (rc) {
         free_copy(c);
         return rc;
@@ -139,6 +148,8 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     c->view.out_first = (const uint32_t *)c->out_first;
     c->view.out_ids = (const uint32_t *)c->out_ids;
     c->view.lds_image = (const uint32_t *)c->lds_image;
+    c->view.tails = (const uint32_t *)c->tails;
+    c->view.tail_bytes = (const uint8_t *)c->tail_bytes;
     a->copies.push_back(c);
     *out = c;
     return PFAC_OK;
@@ -208,18 +219,24 @@ namespace pfac {
 // before old buffers are freed). Clears the look-back words before the epoch could wrap.
 static int ensure_tiles(Workspace *w, uint64_t n, uint32_t span_log2, void *stream) {
     const uint64_t ns = (n + (1ull << span_log2) - 1) >> span_log2;
-    if (ns > w->cap_spans || !w->ts.ctrl) {
+    const uint64_t nrec = ns << rec_cap_log2(span_log2);
+    if (ns > w->cap_spans || nrec > w->cap_recs || !w->ts.ctrl) {
         if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PFAC_EHIP;
+        const uint64_t old_spans = w->cap_spans, old_recs = w->cap_recs;
         free_tiles(w);
-        const uint64_t spans = ns < 1024 ? 1024 : ns + ns / 4;
+        uint64_t spans = ns < 1024 ? 1024 : ns + ns / 4;
+        if (spans < old_spans) spans = old_spans;
+        uint64_t recs = spans << rec_cap_log2(span_log2);
+        if (recs < old_recs) recs = old_recs;
         const uint64_t blocks = (spans + kBlockSpans - 1) / kBlockSpans;
         if (hipMalloc(&w->so.cnt, spans * 8) != hipSuccess) return PFAC_ENOMEM;
         if (hipMalloc(&w->so.nh, spans * 4) != hipSuccess) return PFAC_ENOMEM;
         if (hipMalloc(&w->so.ovf, spans * 4) != hipSuccess) return PFAC_ENOMEM;
-        if (hipMalloc(&w->so.rec, spans * kHCap * 8) != hipSuccess) return PFAC_ENOMEM;
+        if (hipMalloc(&w->so.rec, recs * 8) != hipSuccess) return PFAC_ENOMEM;
         if (hipMalloc(&w->ts.word, blocks * 8) != hipSuccess) return PFAC_ENOMEM;
         if (hipMalloc(&w->ts.ctrl, 16) != hipSuccess) return PFAC_ENOMEM;
         w->cap_spans = spans;
+        w->cap_recs = recs;
         w->cap_tiles = blocks;
         w->launches = kEpochPeriod;  // forces a clear before the first launch
     }
@@ -251,7 +268,8 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, co
     const bool batch = d_offsets != nullptr;
     const uint32_t algo = (a->algo == PFAC_ALGO_PLAIN && !batch) ? PFAC_ALGO_PLAIN : PFAC_ALGO_TILED;
     Workspace *w = nullptr;
-    rc = get_workspace(c, stream, n, algo, a->span_log2, &w);
+    const uint32_t span_log2 = a->span_log2 ? a->span_log2 : auto_span_log2(n, (uint64_t)c->cus * kWaves);
+    rc = get_workspace(c, stream, n, algo, span_log2, &w);
     if (rc) return rc;
     if (ws_out) *ws_out = w;
     uint64_t *cnt = d_count ? d_count : w->d_count;
@@ -261,10 +279,10 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, co
             return PFAC_EHIP;
         return PFAC_OK;
     }
-    const uint64_t ns = (n + (1ull << a->span_log2) - 1) >> a->span_log2;
+    const uint64_t ns = (n + (1ull << span_log2) - 1) >> span_log2;
     const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, (ns + kWaves - 1) / kWaves) : 0u;
     if (launch_tiled(c->view, d_text, n, d_offsets, n_pkts, d_keys, cap, cnt, w->so, w->ts, nullptr, grid,
-                     a->span_log2, s))
+                     span_log2, s))
         return PFAC_EHIP;
     w->launches++;
     return PFAC_OK;
@@ -354,7 +372,6 @@ extern "C" int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, cons
     uint32_t span_log2 = kSpanLog2, grid = 0;
     {
         std::lock_guard<std::mutex> lk(a->mu);
-        span_log2 = a->span_log2;
         grid = a->grid;
         DeviceCopy *c = nullptr;
         int rc = get_copy(a, &c);
@@ -364,6 +381,7 @@ extern "C" int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, cons
         }
         g->device = c->device;
         view = c->view;
+        span_log2 = a->span_log2 ? a->span_log2 : auto_span_log2(max_bytes, (uint64_t)c->cus * kWaves);
     }
     // everything that allocates happens before the capture
     int rc = ensure_tiles(&g->ws, max_bytes, span_log2, stream);
@@ -426,6 +444,8 @@ static int reupload_lds_images(pfac_automaton *a) {
         v.bm = c->view.bm;
         v.out_first = c->view.out_first;
         v.out_ids = c->view.out_ids;
+        v.tails = c->view.tails;
+        v.tail_bytes = c->view.tail_bytes;
         v.lds_image = (const uint32_t *)c->lds_image;
         c->view = v;
     }
@@ -435,8 +455,8 @@ static int reupload_lds_images(pfac_automaton *a) {
 
 static int set_tuning_locked(pfac_automaton *a, const pfac_tuning *t) {
     if (t->algo > PFAC_ALGO_TILED) return PFAC_EINVAL;
-    const uint32_t span = t->span_log2 ? t->span_log2 : kSpanLog2;
-    if (span < kMinSpanLog2 || span > kMaxSpanLog2) return PFAC_EINVAL;
+    const uint32_t span = t->span_log2;  // 0: chosen per scan from the text size
+    if (span && (span < kMinSpanLog2 || span > kMaxSpanLog2)) return PFAC_EINVAL;
     if (t->root_depth != a->req_depth || t->filter_k != a->req_k) {
         int rc = rebuild_lds_image(a, t->root_depth, t->filter_k);
         if (rc) {

@@ -8,24 +8,42 @@
 
 namespace pfac {
 
-constexpr uint32_t kThreads = 1024;  // workgroup: 16 waves sharing one LDS image
+// Build-time shape of the count kernel (the defaults are the measured best on MI355X):
+// threads per workgroup, log2 of the prefilter's bits, survivor queue entries per wave.
+#ifndef PFAC_SCAN_THREADS
+#define PFAC_SCAN_THREADS 1024
+#endif
+#ifndef PFAC_FILTER_LOG2
+#define PFAC_FILTER_LOG2 19
+#endif
+#ifndef PFAC_QCAP
+#define PFAC_QCAP 2048
+#endif
+#ifndef PFAC_SCAN_MIN_WG
+#define PFAC_SCAN_MIN_WG 1
+#endif
+
+constexpr uint32_t kThreads = PFAC_SCAN_THREADS;  // workgroup: waves sharing one LDS image
 constexpr uint32_t kWaves = kThreads / 64;
 constexpr uint32_t kStep = 1024;     // bytes a wave streams per step: 64 lanes x 16
 constexpr uint32_t kSpanLog2 = 14;   // default bytes per work unit (a wave's span): 16 KiB
 constexpr uint32_t kMinSpanLog2 = 10; // a span holds at least one 1 KiB wave step
 constexpr uint32_t kMaxSpanLog2 = 16; // span-local starts are 16-bit
-constexpr uint32_t kQCap = 2048;     // survivor queue; walked when a step might not fit, and at the span end
-constexpr uint32_t kHCap = 256;      // match records kept per span
+constexpr uint32_t kQCap = PFAC_QCAP;  // survivor queue; walked when a step might not fit, and at the span end
+constexpr uint32_t kHCapMinLog2 = 8; // match records kept per span: span / 64, at least 256
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
+constexpr uint32_t kFastRecs = 8;    // a span with at most this many records is written by one lane
 constexpr uint32_t kPlaceThreads = 256;
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
 constexpr uint32_t kWaveLds = kQCap * 2;  // bytes of LDS per wave (survivor queue)
 static_assert(kWaveLds % 16 == 0, "wave regions stay 16-byte aligned");
+static_assert(kQCap >= 128, "a queue holds at least two walk batches");
 
 // Fixed LDS layout of the scan kernel (32-bit words): the filter at offset 0 so a probe's
 // masked hash is its byte address, then the root bitmap and its rank table, then the
 // per-wave queues. Compile-time offsets fold into the LDS instructions.
-constexpr uint32_t kFilterWordsMax = 1u << 14;  // 64 KiB: filters up to 2^19 bits
+constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;
+constexpr uint32_t kFilterWordsMax = 1u << (kMaxFilterLog2 - 5);  // 64 KiB at 2^19 bits
 constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
 constexpr uint32_t kLdsRoot = kFilterWordsMax;
@@ -33,19 +51,32 @@ constexpr uint32_t kLdsRank = kLdsRoot + kRootWordsMax;
 constexpr uint32_t kLdsShort = kLdsRank + kRankWordsMax;
 constexpr uint32_t kLdsQueues = kLdsShort + kRootWordsMax;
 constexpr uint32_t kLdsWords = kLdsQueues + kWaves * kWaveLds / 4;
-constexpr uint32_t kMaxFilterLog2 = 19;
 
 // Per-span results of the count kernel (device memory, owned by a workspace).
 //   cnt[s]   matches in span s          nh[s]   records stored for span s
 //   ovf[s]   span-local start of the first matching start without a record, or ~0
-//   rec[s * kHCap + i]   record i: first terminal node (bits 32..63) | terminals passed
+//   rec[(s << rec_log2) + i]   record i: first terminal node (bits 32..63) | terminals passed
 //                        (16..31, saturated) | span-local start (0..15)
 struct SpanOut {
     uint64_t *cnt;
     uint32_t *nh;
     uint32_t *ovf;
     uint64_t *rec;
+    uint32_t rec_log2;  // log2 of the records per span (set per launch)
 };
+
+// Span length chosen when the tuning leaves it open: the longest power of two (4 to
+// 64 KiB) that still gives every resident wave (`waves`) a span of an n-byte text.
+inline uint32_t auto_span_log2(uint64_t n, uint64_t waves) {
+    uint32_t s = kMaxSpanLog2;
+    while (s > 12 && (n >> s) < waves) s--;
+    return s;
+}
+
+// log2 of the record capacity of a span of 2^span_log2 bytes.
+__host__ __device__ inline uint32_t rec_cap_log2(uint32_t span_log2) {
+    return span_log2 - 6 > kHCapMinLog2 ? span_log2 - 6 : kHCapMinLog2;
+}
 
 // Decoupled look-back state of the placement kernel (device memory, in a workspace).
 //   word[b]   one 64-bit word per block: epoch (bits 44..63) | flag (42..43) | value (0..41)

@@ -129,7 +129,8 @@ uint64_t slot_device_bytes(const pfac_server_config &c, uint32_t span_log2) {
     // the spans of a full batch plus a quarter
     const uint64_t ns = (c.max_batch_bytes + (1ull << span_log2) - 1) >> span_log2;
     const uint64_t spans = ns < 1024 ? 1024 : ns + ns / 4;
-    const uint64_t scratch = spans * (8 + 4 + 4 + 8ull * pfac::kHCap) + spans / pfac::kBlockSpans * 8 + 16 + 1024 * 16;
+    const uint64_t scratch = spans * (8 + 4 + 4 + (8ull << pfac::rec_cap_log2(span_log2))) +
+                             spans / pfac::kBlockSpans * 8 + 16 + 1024 * 16;
     return c.max_batch_bytes + ((uint64_t)c.max_batch_packets + 1) * 8 + 16 + c.key_capacity * 8 + 8 + scratch;
 }
 
@@ -364,7 +365,8 @@ extern "C" int pfac_server_create(pfac_automaton *a, const pfac_server_config *c
     int rc = pfac_upload(a, dev);
     if (rc) return rc;
     // admission by device memory: as many slots as the budget holds
-    const uint64_t per_slot = slot_device_bytes(c, a->span_log2);
+    const uint32_t span_log2 = a->span_log2 ? a->span_log2 : pfac::auto_span_log2(c.max_batch_bytes, 256ull * pfac::kWaves);
+    const uint64_t per_slot = slot_device_bytes(c, span_log2);
     uint64_t budget = c.device_memory_budget;
     if (!budget) {
         size_t free_b = 0, total_b = 0;

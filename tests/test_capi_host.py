@@ -145,7 +145,7 @@ def test_tuning_rebuilds_lds_image_on_host():
     pats = [b"abcdef", b"abxy", b"zzzz", b"qq12"]
     a = pfac.pfac_build(pats, 256)
     t0 = pfac.pfac_get_tuning(a)
-    assert t0["span_log2"] == 14 and t0["root_depth"] == 2 and t0["filter_k"] >= 2
+    assert t0["span_log2"] == 0 and t0["root_depth"] == 2 and t0["filter_k"] >= 2
     pfac.pfac_set_tuning(a, span_log2=11, root_depth=1, filter_k=3)
     t1 = pfac.pfac_get_tuning(a)
     assert (t1["span_log2"], t1["root_depth"], t1["filter_k"]) == (11, 1, 3)

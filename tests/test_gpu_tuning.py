@@ -70,7 +70,7 @@ def test_autotuner_keeps_results_and_reports_its_choice():
     d = _dev(w.data)
     o = _dev(w.offsets.view(np.int64), torch.int64)
     t = pfac.pfac_tune(a, d, o, reps=3)
-    assert t["algo"] == "tiled" and 10 <= t["span_log2"] <= 16 and t["ms"] > 0
+    assert t["algo"] == "tiled" and (t["span_log2"] == 0 or 10 <= t["span_log2"] <= 16) and t["ms"] > 0
     assert pfac.pfac_get_tuning(a) == {k: v for k, v in t.items() if k != "ms"}
     got = pfac.keys_to_numpy(pfac.pfac_scan_batch(a, d, o))
     assert np.array_equal(got, want)
