@@ -538,26 +538,28 @@ struct Scanner {
         const uint64_t top = hi < lim ? hi : lim;
         if (aligned && hiR + 16 <= n) {
             // Steady state: every load is an unconditional 16-byte load with no per-lane
-            // test, three steps ahead; addresses past the span are clamped to its last
+            // test, kPrefetch steps ahead; addresses past the span are clamped to its last
             // step (a repeated load, no bytes past the span). Only the 16 bytes right
             // after the span are read for the last starts' windows.
             const uint64_t lastst = hiR - kStep;
             const uint4 tail = *reinterpret_cast<const uint4 *>(text + hiR);  // uniform address
-            uint4 cur = stream16(text + step + 16 * lane);
-            uint4 nx1 = stream16(text + (step + kStep < lastst ? step + kStep : lastst) + 16 * lane);
-            uint4 nx2 = stream16(text + (step + 2 * kStep < lastst ? step + 2 * kStep : lastst) + 16 * lane);
-            uint32_t pc = PACK2 ? pack2x16(cur) : 0u;
+            uint4 buf[kPrefetch];  // buf[0]: this step; buf[i]: i steps ahead
+#pragma unroll
+            for (uint32_t i = 0; i < kPrefetch; i++)
+                buf[i] = stream16(text + (step + i * kStep < lastst ? step + i * kStep : lastst) + 16 * lane);
+            uint32_t pc = PACK2 ? pack2x16(buf[0]) : 0u;
             const uint32_t ptail = PACK2 ? pack2x16(tail) : 0u;
             for (; step < hiR; step += kStep) {
-                const uint64_t a3 = step + 3 * kStep < lastst ? step + 3 * kStep : lastst;
-                const uint4 nx3 = stream16(text + a3 + 16 * lane);
+                const uint64_t ak = step + kPrefetch * kStep < lastst ? step + kPrefetch * kStep : lastst;
+                const uint4 nxk = stream16(text + ak + 16 * lane);
                 const bool last = step == lastst;
+                const uint4 cur = buf[0];
                 const uint32_t dn = from_next_lane(cur.x);
-                const uint32_t d0n = last ? tail.x : __builtin_amdgcn_readfirstlane(nx1.x);
+                const uint32_t d0n = last ? tail.x : __builtin_amdgcn_readfirstlane(buf[1 % kPrefetch].x);
                 const uint32_t next_d0 = lane == 63 ? d0n : dn;
                 uint32_t pn = 0, c1 = 0;
                 if (PACK2) {
-                    pn = pack2x16(nx1);
+                    pn = pack2x16(buf[1 % kPrefetch]);
                     const uint32_t cn = from_next_lane(pc);
                     const uint32_t p0n = last ? ptail : __builtin_amdgcn_readfirstlane(pn);
                     c1 = lane == 63 ? p0n : cn;
@@ -565,9 +567,9 @@ struct Scanner {
                 uint32_t sl0;
                 const uint32_t m = mask_step(S, step, top, cur, next_d0, pc, c1, &sl0);
                 take(S, m, sl0);
-                cur = nx1;
-                nx1 = nx2;
-                nx2 = nx3;
+#pragma unroll
+                for (uint32_t i = 0; i + 1 < kPrefetch; i++) buf[i] = buf[i + 1];
+                buf[kPrefetch - 1] = nxk;
                 pc = pn;
             }
         } else {

@@ -19,6 +19,9 @@ namespace pfac {
 #ifndef PFAC_QCAP
 #define PFAC_QCAP 2048
 #endif
+#ifndef PFAC_PREFETCH
+#define PFAC_PREFETCH 3
+#endif
 #ifndef PFAC_SCAN_MIN_WG
 #define PFAC_SCAN_MIN_WG 1
 #endif
@@ -29,6 +32,8 @@ constexpr uint32_t kStep = 1024;     // bytes a wave streams per step: 64 lanes 
 constexpr uint32_t kSpanLog2 = 14;   // default bytes per work unit (a wave's span): 16 KiB
 constexpr uint32_t kMinSpanLog2 = 10; // a span holds at least one 1 KiB wave step
 constexpr uint32_t kMaxSpanLog2 = 16; // span-local starts are 16-bit
+constexpr uint32_t kPrefetch = PFAC_PREFETCH;  // text loads in flight per lane, in wave steps (>= 2)
+static_assert(PFAC_PREFETCH >= 2, "the next step's first word comes from the prefetch");
 constexpr uint32_t kQCap = PFAC_QCAP;  // survivor queue; walked when a step might not fit, and at the span end
 constexpr uint32_t kHCapMinLog2 = 8; // match records kept per span: span / 64, at least 256
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
