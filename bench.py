@@ -309,9 +309,11 @@ def main():
     ap.add_argument("--plant-every", type=int, default=0, help="serving: planted variant")
     ap.add_argument("--baseline-steps", type=int, default=3,
                     help="packets: timed passes of the per-packet baseline")
-    ap.add_argument("--mode", default="scan", choices=["scan", "copy"],
+    ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host"],
                     help="copy: a plain device-to-device copy of the workload's text, the "
-                         "reference that scales the HBM byte counters of the scan")
+                         "reference that scales the HBM byte counters of the scan; host: the "
+                         "text starts in host memory (pinned, then pageable) and crosses PCIe "
+                         "inside the timed region")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -337,6 +339,22 @@ def main():
     info = pfac.pfac_table_info(a)
     if args.algo != "auto":
         pfac.pfac_set_tuning(a, algo=args.algo)
+    if args.mode == "host":
+        pinned = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+        pinned.numpy()[:] = w.text
+        res = {}
+        for name, buf in (("pinned", pinned.numpy()), ("pageable", w.text)):
+            pfac.pfac_scan_host(a, buf)  # warm-up: device copy, staging buffers
+            times = []
+            for _ in range(max(1, args.steps)):
+                t0 = time.perf_counter()
+                m = pfac.pfac_scan_host(a, buf)
+                times.append(time.perf_counter() - t0)
+            res[name] = {"ms": round(1e3 * float(np.median(times)), 3),
+                         "gbit_s": round(8.0 * n / float(np.median(times)) / 1e9, 2), "matches": len(m)}
+        print(json.dumps({"mode": "host", "workload": args.workload, "bytes": n, "steps": args.steps,
+                          "chunk_bytes": 64 << 20, "end_to_end": res}), flush=True)
+        return
     texts = [torch.from_numpy(w.text).to(dev) for _ in range(max(1, args.copies))]
     if args.mode == "copy":
         dst = torch.empty_like(texts[0])

@@ -87,7 +87,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
         lk.erase(std::unique(lk.begin(), lk.end()), lk.end());
         const double space = std::pow((double)a->alphabet, (double)k);
         double est = (double)sk.size() / root_nbits + (double)lk.size() / space;
-        if (k > D) est += (double)lk.size() / (double)(1u << kMaxFilterLog2);
+        if (k > D) est += (double)lk.size() / (double)(1u << kMaxFilterLog2) * (double)lk.size() / (double)(1u << kFilter2Log2);
         if (est <= best * 1.001) {
             best = est;
             K = k;
@@ -108,7 +108,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     t.filter_k = K > D ? K : 0;
     t.filter_log2 = flog2;
     t.has_short = any_short ? 1 : 0;
-    const uint32_t filter_words = flog2 ? (1u << flog2) / 32 : 0;
+    const uint32_t filter_words = flog2 ? kFilterWordsMax + kFilter2Words : 0;
     t.root_word = filter_words;
     t.rank_word = filter_words + root_words;
     t.short_word = t.rank_word + rank_words;
@@ -130,7 +130,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     }
     // every depth-D node is a D-prefix of some pattern (D <= shortest length)
     if (run != a->depth_start[D + 1] - a->depth_start[D]) throw std::bad_alloc();
-    for (uint32_t key : fkeys) filter_insert(img, key, flog2);
+    for (uint32_t key : fkeys) filter_insert(img, key, kMaxFilterLog2, kFilter2Log2);
 }
 
 }  // namespace

@@ -112,32 +112,55 @@ struct Trie {
     // Path tail of q: x = offset in tail_bytes, y = length (0: none), z = end node.
     __device__ __forceinline__ uint4 tail(uint32_t q) const { return reinterpret_cast<const uint4 *>(t.tails)[q]; }
 
-    // Whether text[i .. i+len) spells tail_bytes[off .. off+len); 16 byte pairs per round
-    // of loads, all issued before any is compared.
+    // Whether text[i .. i+len) spells tail_bytes[off .. off+len). Both runs are read as
+    // aligned dwords (5 per side per 16 bytes, all issued before any compare) and lined
+    // up with alignbyte. Only dwords that hold at least one compared byte are loaded, so
+    // no load leaves the page of a byte inside the runs.
     __device__ __forceinline__ bool tail_equal(const uint8_t *__restrict__ text, uint64_t i, uint32_t off,
                                                uint32_t len) const {
+        const uintptr_t ta = (uintptr_t)(text + i), pa = (uintptr_t)(t.tail_bytes + off);
+        const uint32_t *tw = reinterpret_cast<const uint32_t *>(ta & ~(uintptr_t)3);
+        const uint32_t *pw = reinterpret_cast<const uint32_t *>(pa & ~(uintptr_t)3);
+        const uint32_t ts = (uint32_t)(ta & 3), ps = (uint32_t)(pa & 3);
+        const uint32_t nt = (ts + len + 3) >> 2, np = (ps + len + 3) >> 2;  // dwords holding compared bytes
         for (uint32_t o = 0; o < len; o += 16) {
+            const uint32_t k0 = o >> 2;  // dword of byte o on both sides (o is a multiple of 16)
+            uint32_t x[5], y[5];
+#pragma unroll
+            for (uint32_t k = 0; k < 5; k++) {
+                x[k] = k0 + k < nt ? tw[k0 + k] : 0u;
+                y[k] = k0 + k < np ? pw[k0 + k] : 0u;
+            }
             uint32_t diff = 0;
 #pragma unroll
-            for (uint32_t k = 0; k < 16; k++)
-                if (o + k < len) diff |= (uint32_t)text[i + o + k] ^ (uint32_t)t.tail_bytes[off + o + k];
+            for (uint32_t k = 0; k < 4; k++) {
+                const uint32_t b = o + 4 * k;  // first compared byte of this group
+                if (b < len) {
+                    const uint32_t m = b + 4 <= len ? 0xffffffffu : (1u << (8 * (len - b))) - 1u;
+                    const uint32_t xt = __builtin_amdgcn_alignbyte(x[k + 1], x[k], ts);
+                    const uint32_t yp = __builtin_amdgcn_alignbyte(y[k + 1], y[k], ps);
+                    diff |= (xt ^ yp) & m;
+                }
+            }
             if (diff) return false;
         }
         return true;
     }
 
-    // One move of a walk at node q, text position i < end: along q's whole path tail when
-    // it has one, else one symbol by Eq. 1. False when the walk ends here.
+    // One move of a walk at node q, text position i < end: the next symbol by Eq. 1, and
+    // when q has a path tail and that symbol starts it, the rest of the tail at once. A
+    // mismatch on the first symbol thus costs no more than a plain step. False when the
+    // walk ends here.
     __device__ __forceinline__ bool advance(uint32_t &q, uint64_t &i, uint4 tl, const uint8_t *__restrict__ text,
                                             uint32_t c, uint64_t end) const {
-        if (tl.y) {
-            if (i + tl.y > end || !tail_equal(text, i, tl.x, tl.y)) return false;
+        const int64_t nq = child(q, c);
+        if (nq < 0) return false;
+        if (tl.y > 1) {
+            if (i + tl.y > end || !tail_equal(text, i + 1, tl.x + 1, tl.y - 1)) return false;
             q = tl.z;
             i += tl.y;
             return true;
         }
-        const int64_t nq = child(q, c);
-        if (nq < 0) return false;
         q = (uint32_t)nq;
         i++;
         return true;
@@ -251,8 +274,18 @@ __device__ __forceinline__ uint64_t packet_end(const uint64_t *__restrict__ offs
     return offsets[lo + 1];
 }
 
-// 16 text bytes at an aligned address.
-__device__ __forceinline__ uint4 stream16(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+// Text stream loads through a buffer resource over the text: the per-step offset is a
+// scalar (wave-uniform) register and the lane's 16-byte slot a fixed vector offset, so a
+// load costs no vector address arithmetic. 0x20000: the raw-buffer word 3 of gfx9.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t text_rsrc(const uint8_t *text, uint64_t n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(text), (short)0,
+                                             (int)(n < 0xffffffffull ? n : 0xffffffffull), 0x00020000);
+}
+__device__ __forceinline__ uint4 stream16(__amdgpu_buffer_rsrc_t rs, uint32_t lane_off, uint32_t step_off) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, lane_off, __builtin_amdgcn_readfirstlane(step_off), 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
 
 // 16 bytes at p; bytes at or past `lim` read as zero (no load at all when p >= lim).
 // Vector load when the 16 bytes are whole and aligned.
@@ -287,22 +320,23 @@ __device__ __forceinline__ uint32_t pack2x16(uint4 v) {
     return c;
 }
 
-// One prefilter probe: the filter word's byte offset is the masked high half of
-// key * kFilterMul (the filter sits at LDS offset 0), the bit is key & 31.
-__device__ __forceinline__ uint32_t probe(const uint32_t *img, uint32_t key, uint32_t amask) {
-    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) +
-                                                          (__umulhi(key, kFilterMul) & amask));
+// First prefilter probe of a key: the word at the masked high half of key * kFilterMul
+// in the first-probe region, bit key & 31.
+__device__ __forceinline__ uint32_t probe(const uint32_t *img, uint32_t key) {
+    const uint32_t off = (__umulhi(key, kFilterMul) & kAmask1) + kLdsF1 * 4;
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + off);
     return __builtin_amdgcn_ubfe(w, key, 1);
 }
 
-// Second probe of a key that passed the first (see filter2_hash).
-__device__ __forceinline__ uint32_t probe2(const uint32_t *img, uint32_t key, uint32_t amask) {
-    const uint32_t h = filter2_hash(key);
-    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + (h & amask));
+// Second probe, for a key that passed the first: the second-probe region, bit = the top
+// five bits of the high half of key * kFilterMul2.
+__device__ __forceinline__ uint32_t probe2(const uint32_t *img, uint32_t key) {
+    const uint32_t h = __umulhi(key, kFilterMul2);
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + (h & kAmask2));
     return (w >> (h >> 27)) & 1u;
 }
 
-// Four bytes starting at byte j (0..15) of the 20 bytes d0..d4 (little-endian words).
+// Four bytes starting at byte j (0..15) of the 20 bytes v, d4 (little-endian words).
 __device__ __forceinline__ uint32_t bytes4_at(uint4 v, uint32_t d4, uint32_t j) {
     const uint32_t qd = j >> 2;
     const uint32_t lo = qd == 0 ? v.x : qd == 1 ? v.y : qd == 2 ? v.z : v.w;
@@ -325,39 +359,38 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
     if (!PACK2) {
         const uint32_t d[5] = {cur.x, cur.y, cur.z, cur.w, next_d0};
         if (t.filter_k == 4 && !t.has_short) {
-            const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
+            // one chain of shift-or steps, start 15 first, so each start costs one insert
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
+            for (int j = 15; j >= 0; j--) {
                 const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
-                mask |= probe(img, x, amask) << j;
+                mask = (mask << 1) | probe(img, x);
             }
             uint32_t rem = mask;
             while (rem) {  // second probe of the few that passed
                 const uint32_t j = __builtin_ctz(rem);
                 rem &= rem - 1;
-                mask &= ~((probe2(img, bytes4_at(cur, next_d0, j), amask) ^ 1u) << j);
+                mask &= ~((probe2(img, bytes4_at(cur, next_d0, j)) ^ 1u) << j);
             }
         } else if (t.filter_k) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
-            const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
             const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : (1u << (8 * t.filter_k)) - 1u;
             const uint32_t *shrt = img + kLdsShort;
             const bool two = t.root_depth == 2, sh = t.has_short;
             uint32_t ms = 0;
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
+            for (int j = 15; j >= 0; j--) {
                 const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
-                mask |= probe(img, x & kmask, amask) << j;
+                mask = (mask << 1) | probe(img, x & kmask);
                 if (sh) {
                     const uint32_t key = two ? (((x & 0xffu) << 8) | ((x >> 8) & 0xffu)) : (x & 0xffu);
-                    ms |= probe_root(shrt, key) << j;
+                    ms = (ms << 1) | probe_root(shrt, key);
                 }
             }
             uint32_t rem = mask & ~ms;
             while (rem) {
                 const uint32_t j = __builtin_ctz(rem);
                 rem &= rem - 1;
-                mask &= ~((probe2(img, bytes4_at(cur, next_d0, j) & kmask, amask) ^ 1u) << j);
+                mask &= ~((probe2(img, bytes4_at(cur, next_d0, j) & kmask) ^ 1u) << j);
             }
             mask |= ms;
         } else {
@@ -365,10 +398,10 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
             const uint32_t *root = img + kLdsRoot;
             const bool two = t.root_depth == 2;
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
+            for (int j = 15; j >= 0; j--) {
                 const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
                 const uint32_t key = two ? (((x & 0xffu) << 8) | ((x >> 8) & 0xffu)) : (x & 0xffu);
-                mask |= probe_root(root, key) << j;
+                mask = (mask << 1) | probe_root(root, key);
             }
         }
     } else {
@@ -377,31 +410,30 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         const uint32_t rs = 32 - 2 * K;
         if (t.filter_k) {
             // k-gram filter, plus the short bitmap (D-grams) for patterns shorter than k
-            const uint32_t amask = ((1u << (t.filter_log2 - 5)) - 1u) << 2;
             const uint32_t *shrt = img + kLdsShort;
             const uint32_t rsd = 32 - 2 * t.root_depth;
             const bool sh = t.has_short;
             uint32_t ms = 0;
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
+            for (int j = 15; j >= 0; j--) {
                 const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
-                mask |= probe(img, rs >= 32 ? top : top >> rs, amask) << j;
-                if (sh) ms |= probe_root(shrt, top >> rsd) << j;
+                mask = (mask << 1) | probe(img, rs >= 32 ? top : top >> rs);
+                if (sh) ms = (ms << 1) | probe_root(shrt, top >> rsd);
             }
             uint32_t rem = mask & ~ms;
             while (rem) {
                 const uint32_t j = __builtin_ctz(rem);
                 rem &= rem - 1;
                 const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
-                mask &= ~((probe2(img, rs >= 32 ? top : top >> rs, amask) ^ 1u) << j);
+                mask &= ~((probe2(img, rs >= 32 ? top : top >> rs) ^ 1u) << j);
             }
             mask |= ms;
         } else {
             const uint32_t *root = img + kLdsRoot;
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
+            for (int j = 15; j >= 0; j--) {
                 const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
-                mask |= probe_root(root, top >> rs) << j;
+                mask = (mask << 1) | probe_root(root, top >> rs);
             }
         }
     }
@@ -543,15 +575,17 @@ struct Scanner {
             // after the span are read for the last starts' windows.
             const uint64_t lastst = hiR - kStep;
             const uint4 tail = *reinterpret_cast<const uint4 *>(text + hiR);  // uniform address
+            const __amdgpu_buffer_rsrc_t rs = text_rsrc(text, n);
+            const uint32_t loff = 16 * lane;
             uint4 buf[kPrefetch];  // buf[0]: this step; buf[i]: i steps ahead
 #pragma unroll
             for (uint32_t i = 0; i < kPrefetch; i++)
-                buf[i] = stream16(text + (step + i * kStep < lastst ? step + i * kStep : lastst) + 16 * lane);
+                buf[i] = stream16(rs, loff, (uint32_t)(step + i * kStep < lastst ? step + i * kStep : lastst));
             uint32_t pc = PACK2 ? pack2x16(buf[0]) : 0u;
             const uint32_t ptail = PACK2 ? pack2x16(tail) : 0u;
             for (; step < hiR; step += kStep) {
                 const uint64_t ak = step + kPrefetch * kStep < lastst ? step + kPrefetch * kStep : lastst;
-                const uint4 nxk = stream16(text + ak + 16 * lane);
+                const uint4 nxk = stream16(rs, loff, (uint32_t)ak);
                 const bool last = step == lastst;
                 const uint4 cur = buf[0];
                 const uint32_t dn = from_next_lane(cur.x);
@@ -631,7 +665,9 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     }
     __syncthreads();  // the only barrier: waves run independently from here
 
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    // the wave index through a scalar register: everything derived from it (span, step,
+    // load offsets) then stays in scalar registers
+    const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint16_t *wq = reinterpret_cast<uint16_t *>(img + kLdsQueues) + wave * kQCap;
     Scanner<LAYOUT, PACK2, SEG> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
                                    offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0};
@@ -780,34 +816,57 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                 }
             }
         }
-        // the other spans: waves 1.. take every (kPlaceWaves - 1)-th
-        for (uint32_t i = wave - 1; wave > 0 && i < kBlockSpans; i += kPlaceWaves - 1) {
+        // the other spans: every wave takes every kPlaceWaves-th (wave 0 after its lanes'
+        // spans above)
+        for (uint32_t i = wave; i < kBlockSpans; i += kPlaceWaves) {
             const uint32_t sp = blk * kBlockSpans + i;
             if (span_cls[i] != 2) continue;
             uint64_t run = span_off[i];
             const uint64_t a = (uint64_t)sp << span_log2;
             const uint64_t b = a + span_len < n ? a + span_len : n;
             const uint32_t nh = so.nh[sp], ovf = so.ovf[sp];
-            for (uint32_t h0 = 0; h0 < nh; h0 += 64) {
-                const bool on = h0 + lane < nh;
-                const uint64_t rec = on ? so.rec[((size_t)sp << so.rec_log2) + h0 + lane] : 0;
-                const uint64_t s = a + (rec & 0xffffu);
-                const uint32_t nterm = (uint32_t)(rec >> 16) & 0xffffu, q0 = (uint32_t)(rec >> 32);
-                const uint64_t end = on ? end_of(s) : 0;
-                uint32_t c = 0;
-                if (on) c = nterm == 1 ? T.ids(q0) : T.walk_from(0, text, s, end).cnt;
-                const uint32_t incl = wave_incl_scan(c);
-                const uint64_t o = run + incl - c;
-                if (c && o + c <= cap) {
-                    if (nterm == 1) {
-                        const uint64_t hi = s << 32;
-                        const uint32_t f = t.out_first[q0];
-                        for (uint32_t x = 0; x < c; x++) keys[o + x] = hi | t.out_ids[f + x];
-                    } else {
-                        T.emit_walk(text, s, end, keys, o, c);
-                    }
+            // records kRecRounds x 64 at a time: every load of a round is issued before
+            // any of its results is used, so a span with many records pays a few memory
+            // latencies per 256 records rather than per 64
+            for (uint32_t h0 = 0; h0 < nh; h0 += 64 * kRecRounds) {
+                uint64_t rec[kRecRounds];
+                uint32_t f[kRecRounds], e[kRecRounds];
+#pragma unroll
+                for (uint32_t u = 0; u < kRecRounds; u++) {
+                    const uint32_t h = h0 + 64 * u + lane;
+                    rec[u] = h < nh ? so.rec[((size_t)sp << so.rec_log2) + h] : 0;
                 }
-                run += __builtin_amdgcn_readlane(incl, 63);
+#pragma unroll
+                for (uint32_t u = 0; u < kRecRounds; u++) {
+                    const uint32_t q0 = (uint32_t)(rec[u] >> 32);
+                    const bool one = h0 + 64 * u + lane < nh && ((rec[u] >> 16) & 0xffffu) == 1;
+                    f[u] = one ? t.out_first[q0] : 0u;
+                    e[u] = one ? t.out_first[q0 + 1] : 0u;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kRecRounds; u++) {
+                    if (h0 + 64 * u >= nh) break;  // wave-uniform
+                    const bool on = h0 + 64 * u + lane < nh;
+                    const uint64_t s = a + (rec[u] & 0xffffu);
+                    const uint32_t nterm = (uint32_t)(rec[u] >> 16) & 0xffffu;
+                    uint64_t end = 0;
+                    uint32_t c = e[u] - f[u];
+                    if (on && nterm != 1) {  // several terminals: walk again from the root
+                        end = end_of(s);
+                        c = T.walk_from(0, text, s, end).cnt;
+                    }
+                    const uint32_t incl = wave_incl_scan(c);
+                    const uint64_t o = run + incl - c;
+                    if (c && o + c <= cap) {
+                        if (nterm == 1) {
+                            const uint64_t hi = s << 32;
+                            for (uint32_t x = 0; x < c; x++) keys[o + x] = hi | t.out_ids[f[u] + x];
+                        } else {
+                            T.emit_walk(text, s, end, keys, o, c);
+                        }
+                    }
+                    run += __builtin_amdgcn_readlane(incl, 63);
+                }
             }
             if (ovf != kNone) {
                 // more matching starts than records: walk every start from the first one

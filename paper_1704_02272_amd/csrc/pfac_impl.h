@@ -65,7 +65,7 @@ struct DevTable {
     uint32_t root_base;         // index of the first depth-D node
     uint32_t filter_k;          // k (symbols per filter key); 0 = no hashed filter
     uint32_t has_short;         // 1: some pattern is shorter than k (short bitmap used)
-    uint32_t filter_log2;       // log2(filter bits)
+    uint32_t filter_log2;       // log2(bits of the first-probe region); 0 = no filter
     uint32_t lds_words;         // total image size in 32-bit words
     uint32_t root_word;         // word offset of the root bitmap
     uint32_t rank_word;         // word offset of the rank table
@@ -73,26 +73,23 @@ struct DevTable {
 };
 
 constexpr uint32_t kFilterMul = 0x9E3779B1u;  // multiplicative hash (golden ratio)
+constexpr uint32_t kFilterMul2 = 0x85EBCA6Bu; // second hash (MurmurHash3 finalizer constant)
 
-// Prefilter over k-gram keys, 2^log2_bits bits (log2_bits in 13..22): a key sets one
-// bit. Word = bits 2.. of the high half of key * kFilterMul (masked to the word count),
-// so the masked high half is directly the word's byte offset; bit = key & 31. The
+// Prefilter over k-gram keys: a two-probe Bloom filter split into two regions, probe 2's
+// region of 2^log2_b bits first, then probe 1's region of 2^log2_a bits. A key sets one bit
+// in each. Probe 1: word from the high half of key * kFilterMul masked to the region
+// (the masked value is the word's byte offset in the region), bit = key & 31. Probe 2: the
+// same with kFilterMul2, bit = the top five bits of that high half. A key passes only if
+// both bits are set; the scan takes probe 2 only for starts that pass probe 1. The
 // builder and the kernels must agree bit for bit.
-__host__ __device__ inline uint32_t filter_byte_offset(uint32_t key, uint32_t log2_bits) {
-    const uint32_t hi = (uint32_t)(((uint64_t)key * kFilterMul) >> 32);
-    return hi & (((1u << (log2_bits - 5)) - 1u) << 2);
+__host__ __device__ inline uint32_t filter_hi(uint32_t key, uint32_t mul) {
+    return (uint32_t)(((uint64_t)key * mul) >> 32);
 }
-// Second hash of the same key (a two-probe Bloom filter): word from the high half of
-// key * kFilterMul2 the same way, bit = its top five bits. A key is present only if both
-// bits are set; the scan tests the second bit only for starts that passed the first.
-constexpr uint32_t kFilterMul2 = 0x85EBCA6Bu;  // odd multiplier (MurmurHash3 finalizer)
-__host__ __device__ inline uint32_t filter2_hash(uint32_t key) {
-    return (uint32_t)(((uint64_t)key * kFilterMul2) >> 32);
-}
-inline void filter_insert(uint32_t *F, uint32_t key, uint32_t log2_bits) {
-    F[filter_byte_offset(key, log2_bits) >> 2] |= 1u << (key & 31);
-    const uint32_t h2 = filter2_hash(key);
-    F[(h2 & (((1u << (log2_bits - 5)) - 1u) << 2)) >> 2] |= 1u << (h2 >> 27);
+inline void filter_insert(uint32_t *F, uint32_t key, uint32_t log2_a, uint32_t log2_b) {
+    const uint32_t wa = 1u << (log2_a - 5), wb = 1u << (log2_b - 5);
+    F[wb + ((filter_hi(key, kFilterMul) >> 2) & (wa - 1u))] |= 1u << (key & 31);
+    const uint32_t h2 = filter_hi(key, kFilterMul2);
+    F[(h2 >> 2) & (wb - 1u)] |= 1u << (h2 >> 27);
 }
 
 struct Workspace;  // per (device, stream) scratch, defined in the runtime

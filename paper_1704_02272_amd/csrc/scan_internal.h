@@ -16,8 +16,11 @@ namespace pfac {
 #ifndef PFAC_FILTER_LOG2
 #define PFAC_FILTER_LOG2 19
 #endif
+#ifndef PFAC_FILTER2_LOG2
+#define PFAC_FILTER2_LOG2 18
+#endif
 #ifndef PFAC_QCAP
-#define PFAC_QCAP 2048
+#define PFAC_QCAP 512
 #endif
 #ifndef PFAC_PREFETCH
 #define PFAC_PREFETCH 3
@@ -38,20 +41,28 @@ constexpr uint32_t kQCap = PFAC_QCAP;  // survivor queue; walked when a step mig
 constexpr uint32_t kHCapMinLog2 = 8; // match records kept per span: span / 64, at least 256
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
 constexpr uint32_t kFastRecs = 8;    // a span with at most this many records is written by one lane
+constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement wave issues together
 constexpr uint32_t kPlaceThreads = 256;
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
 constexpr uint32_t kWaveLds = kQCap * 2;  // bytes of LDS per wave (survivor queue)
 static_assert(kWaveLds % 16 == 0, "wave regions stay 16-byte aligned");
 static_assert(kQCap >= 128, "a queue holds at least two walk batches");
 
-// Fixed LDS layout of the scan kernel (32-bit words): the filter at offset 0 so a probe's
-// masked hash is its byte address, then the root bitmap and its rank table, then the
-// per-wave queues. Compile-time offsets fold into the LDS instructions.
-constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;
-constexpr uint32_t kFilterWordsMax = 1u << (kMaxFilterLog2 - 5);  // 64 KiB at 2^19 bits
+// Fixed LDS layout of the scan kernel (32-bit words): the prefilter's second-probe
+// region at offset 0, its first-probe region right after (its offset, 32 KiB, fits the
+// LDS instructions' immediate offset), then the root bitmap and its rank table, the
+// short-pattern bitmap and the per-wave queues. A probe's masked hash plus the region's
+// compile-time offset is its byte address.
+constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;    // first-probe region: 2^19 bits
+constexpr uint32_t kFilter2Log2 = PFAC_FILTER2_LOG2;     // second-probe region: 2^18 bits
+constexpr uint32_t kFilterWordsMax = 1u << (kMaxFilterLog2 - 5);
+constexpr uint32_t kFilter2Words = 1u << (kFilter2Log2 - 5);
+constexpr uint32_t kLdsF1 = kFilter2Words;                // word offset of the first-probe region
+constexpr uint32_t kAmask1 = (kFilterWordsMax - 1u) << 2; // byte-offset masks of the regions
+constexpr uint32_t kAmask2 = (kFilter2Words - 1u) << 2;
 constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
-constexpr uint32_t kLdsRoot = kFilterWordsMax;
+constexpr uint32_t kLdsRoot = kLdsF1 + kFilterWordsMax;
 constexpr uint32_t kLdsRank = kLdsRoot + kRootWordsMax;
 constexpr uint32_t kLdsShort = kLdsRank + kRankWordsMax;
 constexpr uint32_t kLdsQueues = kLdsShort + kRootWordsMax;
