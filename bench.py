@@ -41,7 +41,9 @@ WORKLOADS = {
 }
 
 KERNEL_SOURCES = ["paper_1704_02272_amd/csrc/kernels_scan.hip",
-                  "paper_1704_02272_amd/csrc/kernels_plain.hip"]
+                  "paper_1704_02272_amd/csrc/kernels_plain.hip",
+                  "paper_1704_02272_amd/csrc/scan_internal.h",
+                  "paper_1704_02272_amd/csrc/pfac_impl.h"]
 
 
 def source_digest() -> str:

@@ -321,7 +321,7 @@ PFAC_API void pfac_server_destroy(pfac_server *s);
  *               (persistent count kernel with the LDS prefilter and root image, then the
  *               placement kernel).
  *   grid        workgroups of the count kernel (0 = as many as are resident at once).
- *   span_log2   log2 of the bytes one wave scans as a unit (its chunk): 10..16; 0 = per
+ *   span_log2   log2 of the bytes one wave scans as a unit (its chunk): 11..16; 0 = per
  *               scan, the longest span (4..64 KiB) that still gives every resident wave
  *               one. Smaller spans spread small texts over more waves; a span keeps up to
  *               max(256, span / 64) match records in per-stream scratch.

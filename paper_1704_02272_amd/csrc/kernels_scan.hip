@@ -548,18 +548,63 @@ struct Scanner {
         }
     }
 
-    // Survivor mask of the step at `step` (lane's 16 starts), cut to [S.a, top).
-    __device__ __forceinline__ uint32_t mask_step(const SpanState &S, uint64_t step, uint64_t top, uint4 cur,
-                                                  uint32_t next_d0, uint32_t pc, uint32_t c1, uint32_t *sl0_out) const {
+    // A lane's bytes of one step: kLaneBytes (16 or 32) consecutive text bytes, with the
+    // two-bit codes of each 16 when symbols are two-bit codes.
+    struct Chunk {
+        uint4 v[kLaneBytes / 16];
+    };
+    __device__ __forceinline__ Chunk chunk_buffer(__amdgpu_buffer_rsrc_t rs, uint32_t loff, uint32_t soff) const {
+        Chunk c;
+#pragma unroll
+        for (uint32_t h = 0; h < kLaneBytes / 16; h++) c.v[h] = stream16(rs, loff + 16 * h, soff);
+        return c;
+    }
+    __device__ __forceinline__ Chunk chunk_guarded(uint64_t p, uint64_t ld) const {
+        Chunk c;
+#pragma unroll
+        for (uint32_t h = 0; h < kLaneBytes / 16; h++) c.v[h] = load16(text, p + 16 * h, ld, aligned);
+        return c;
+    }
+
+    // Survivor mask of this lane's kLaneBytes starts at `step` (bit j = start
+    // step + kLaneBytes * lane + j), cut to [S.a, top). next_d0 / next_c: first word / first
+    // two-bit codes of the bytes after this lane's.
+    __device__ __forceinline__ uint32_t mask_step(const SpanState &S, uint64_t step, uint64_t top, const Chunk &cur,
+                                                  uint32_t next_d0, uint32_t next_c, uint32_t *sl0_out) const {
         const uint32_t lane = lane_id();
-        uint32_t m = prefilter16<PACK2>(t, W.img, cur, next_d0, pc, c1);
-        const uint32_t sl0 = (uint32_t)(step - S.a) + 16 * lane;  // span-local start of bit 0
+        uint32_t m = 0;
+#pragma unroll
+        for (uint32_t h = 0; h < kLaneBytes / 16; h++) {
+            const bool lasth = h + 1 == kLaneBytes / 16;
+            const uint32_t nd = lasth ? next_d0 : cur.v[h + 1].x;
+            const uint32_t c0 = PACK2 ? pack2x16(cur.v[h]) : 0u;
+            const uint32_t c1 = PACK2 ? (lasth ? next_c : pack2x16(cur.v[h + 1])) : 0u;
+            m |= prefilter16<PACK2>(t, W.img, cur.v[h], nd, c0, c1) << (16 * h);
+        }
+        const uint32_t sl0 = (uint32_t)(step - S.a) + kLaneBytes * lane;  // span-local start of bit 0
         if (step + kStep > top) {  // last step: keep starts below top
             const uint64_t s0 = S.a + sl0;
-            if (s0 + 16 > top) m &= s0 >= top ? 0u : ((1u << (uint32_t)(top - s0)) - 1u);
+            if (s0 + kLaneBytes > top) m &= s0 >= top ? 0u : (uint32_t)((1ull << (uint32_t)(top - s0)) - 1ull);
         }
         *sl0_out = sl0;
         return m;
+    }
+
+    // First word and first two-bit codes of the next lane's chunk (the last lane takes
+    // them from the next step's lane 0, or from `after` past the span's last step).
+    __device__ __forceinline__ void next_lane_head(const Chunk &cur, const Chunk &nxt, bool last, uint4 after,
+                                                   uint32_t *d0, uint32_t *c0) const {
+        const uint32_t lane = lane_id();
+        const uint32_t dn = from_next_lane(cur.v[0].x);
+        const uint32_t d0n = last ? after.x : __builtin_amdgcn_readfirstlane(nxt.v[0].x);
+        *d0 = lane == 63 ? d0n : dn;
+        if (PACK2) {
+            const uint32_t cn = from_next_lane(pack2x16(cur.v[0]));
+            const uint32_t c0n = last ? pack2x16(after) : __builtin_amdgcn_readfirstlane(pack2x16(nxt.v[0]));
+            *c0 = lane == 63 ? c0n : cn;
+        } else {
+            *c0 = 0;
+        }
     }
 
     // Count the span [S.a, hi).
@@ -574,63 +619,40 @@ struct Scanner {
             // step (a repeated load, no bytes past the span). Only the 16 bytes right
             // after the span are read for the last starts' windows.
             const uint64_t lastst = hiR - kStep;
-            const uint4 tail = *reinterpret_cast<const uint4 *>(text + hiR);  // uniform address
+            const uint4 after = *reinterpret_cast<const uint4 *>(text + hiR);  // uniform address
             const __amdgpu_buffer_rsrc_t rs = text_rsrc(text, n);
-            const uint32_t loff = 16 * lane;
-            uint4 buf[kPrefetch];  // buf[0]: this step; buf[i]: i steps ahead
+            const uint32_t loff = kLaneBytes * lane;
+            Chunk buf[kPrefetch];  // buf[0]: this step; buf[i]: i steps ahead
 #pragma unroll
             for (uint32_t i = 0; i < kPrefetch; i++)
-                buf[i] = stream16(rs, loff, (uint32_t)(step + i * kStep < lastst ? step + i * kStep : lastst));
-            uint32_t pc = PACK2 ? pack2x16(buf[0]) : 0u;
-            const uint32_t ptail = PACK2 ? pack2x16(tail) : 0u;
+                buf[i] = chunk_buffer(rs, loff, (uint32_t)(step + i * kStep < lastst ? step + i * kStep : lastst));
             for (; step < hiR; step += kStep) {
                 const uint64_t ak = step + kPrefetch * kStep < lastst ? step + kPrefetch * kStep : lastst;
-                const uint4 nxk = stream16(rs, loff, (uint32_t)ak);
-                const bool last = step == lastst;
-                const uint4 cur = buf[0];
-                const uint32_t dn = from_next_lane(cur.x);
-                const uint32_t d0n = last ? tail.x : __builtin_amdgcn_readfirstlane(buf[1 % kPrefetch].x);
-                const uint32_t next_d0 = lane == 63 ? d0n : dn;
-                uint32_t pn = 0, c1 = 0;
-                if (PACK2) {
-                    pn = pack2x16(buf[1 % kPrefetch]);
-                    const uint32_t cn = from_next_lane(pc);
-                    const uint32_t p0n = last ? ptail : __builtin_amdgcn_readfirstlane(pn);
-                    c1 = lane == 63 ? p0n : cn;
-                }
+                const Chunk nxk = chunk_buffer(rs, loff, (uint32_t)ak);
+                uint32_t nd, nc;
+                next_lane_head(buf[0], buf[1 % kPrefetch], step == lastst, after, &nd, &nc);
                 uint32_t sl0;
-                const uint32_t m = mask_step(S, step, top, cur, next_d0, pc, c1, &sl0);
+                const uint32_t m = mask_step(S, step, top, buf[0], nd, nc, &sl0);
                 take(S, m, sl0);
 #pragma unroll
                 for (uint32_t i = 0; i + 1 < kPrefetch; i++) buf[i] = buf[i + 1];
                 buf[kPrefetch - 1] = nxk;
-                pc = pn;
             }
         } else {
             // End of the text, or an unaligned text: guarded loads, zero past the end.
             const uint64_t need = hi + (PACK2 ? 16 : 4);
             const uint64_t ld = need < n ? need : n;
-            uint4 cur = load16(text, step + 16 * lane, ld, aligned);
-            uint4 nx1 = load16(text, step + kStep + 16 * lane, ld, aligned);
-            uint32_t pc = PACK2 ? pack2x16(cur) : 0u;
+            Chunk cur = chunk_guarded(step + kLaneBytes * lane, ld);
+            Chunk nx1 = chunk_guarded(step + kStep + kLaneBytes * lane, ld);
             for (; step < hi; step += kStep) {
-                const uint4 nx2 = load16(text, step + 2 * kStep + 16 * lane, ld, aligned);
-                const uint32_t dn = from_next_lane(cur.x);
-                const uint32_t d0n = __builtin_amdgcn_readfirstlane(nx1.x);
-                const uint32_t next_d0 = lane == 63 ? d0n : dn;
-                uint32_t pn = 0, c1 = 0;
-                if (PACK2) {
-                    pn = pack2x16(nx1);
-                    const uint32_t cn = from_next_lane(pc);
-                    const uint32_t p0n = __builtin_amdgcn_readfirstlane(pn);
-                    c1 = lane == 63 ? p0n : cn;
-                }
+                const Chunk nx2 = chunk_guarded(step + 2 * kStep + kLaneBytes * lane, ld);
+                uint32_t nd, nc;
+                next_lane_head(cur, nx1, false, make_uint4(0u, 0u, 0u, 0u), &nd, &nc);
                 uint32_t sl0;
-                const uint32_t m = mask_step(S, step, top, cur, next_d0, pc, c1, &sl0);
+                const uint32_t m = mask_step(S, step, top, cur, nd, nc, &sl0);
                 take(S, m, sl0);
                 cur = nx1;
                 nx1 = nx2;
-                pc = pn;
             }
         }
         drain(S);

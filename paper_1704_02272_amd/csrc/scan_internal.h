@@ -23,7 +23,7 @@ namespace pfac {
 #define PFAC_QCAP 512
 #endif
 #ifndef PFAC_PREFETCH
-#define PFAC_PREFETCH 3
+#define PFAC_PREFETCH 2
 #endif
 #ifndef PFAC_SCAN_MIN_WG
 #define PFAC_SCAN_MIN_WG 1
@@ -31,9 +31,14 @@ namespace pfac {
 
 constexpr uint32_t kThreads = PFAC_SCAN_THREADS;  // workgroup: waves sharing one LDS image
 constexpr uint32_t kWaves = kThreads / 64;
-constexpr uint32_t kStep = 1024;     // bytes a wave streams per step: 64 lanes x 16
+#ifndef PFAC_LANE_BYTES
+#define PFAC_LANE_BYTES 32
+#endif
+constexpr uint32_t kLaneBytes = PFAC_LANE_BYTES;  // bytes (starts) a lane takes per step: 16 or 32
+static_assert(kLaneBytes == 16 || kLaneBytes == 32, "a lane's starts fit one 32-bit mask");
+constexpr uint32_t kStep = 64 * kLaneBytes;  // bytes a wave streams per step
 constexpr uint32_t kSpanLog2 = 14;   // default bytes per work unit (a wave's span): 16 KiB
-constexpr uint32_t kMinSpanLog2 = 10; // a span holds at least one 1 KiB wave step
+constexpr uint32_t kMinSpanLog2 = kLaneBytes == 16 ? 10 : 11;  // a span holds at least one wave step
 constexpr uint32_t kMaxSpanLog2 = 16; // span-local starts are 16-bit
 constexpr uint32_t kPrefetch = PFAC_PREFETCH;  // text loads in flight per lane, in wave steps (>= 2)
 static_assert(PFAC_PREFETCH >= 2, "the next step's first word comes from the prefetch");

@@ -152,9 +152,9 @@ def test_tuning_rebuilds_lds_image_on_host():
     info = pfac.pfac_table_info(a)
     assert info["root_depth"] == 1 and info["filter_k"] == 3
     # out of range: shorter than the root depth, longer than the shortest pattern allows,
-    # a span outside 10..16; the previous tuning stays in force
+    # a span outside 11..16; the previous tuning stays in force
     for bad in (dict(root_depth=1, filter_k=5), dict(root_depth=3), dict(root_depth=2, filter_k=1),
-                dict(span_log2=9), dict(span_log2=17)):
+                dict(span_log2=10), dict(span_log2=17)):
         with pytest.raises(pfac.PfacError) as e:
             pfac.pfac_set_tuning(a, **bad)
         assert e.value.code == pfac.PFAC_EINVAL
