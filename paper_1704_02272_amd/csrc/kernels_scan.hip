@@ -79,8 +79,10 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 
 // ------------------------------------------------------------------------ the walk
 // Result of one walk: how many pattern ids it passed, how many terminals, the first one.
+// A walk's pattern-id count, the number of terminals it passed, and the ids of the first
+// one: out_ids[f0 .. f0 + k0).
 struct WalkResult {
-    uint32_t cnt, nterm, term0;
+    uint32_t cnt, nterm, f0, k0;
 };
 
 template <int LAYOUT>
@@ -169,12 +171,16 @@ struct Trie {
     // Walk from node q at text position i (end exclusive): count ids of every terminal,
     // including q itself.
     __device__ WalkResult walk_from(uint32_t q, const uint8_t *__restrict__ text, uint64_t i, uint64_t end) const {
-        WalkResult r{0, 0, 0};
+        WalkResult r{0, 0, 0, 0};
         for (;;) {
             const uint4 tl = tail(q);
             if (is_term(q)) {
-                r.cnt += ids(q);
-                r.term0 = r.nterm == 0 ? q : r.term0;
+                const uint32_t f = t.out_first[q], k = t.out_first[q + 1] - f;
+                r.cnt += k;
+                if (r.nterm == 0) {
+                    r.f0 = f;
+                    r.k0 = k;
+                }
                 r.nterm++;
             }
             if (i >= end) break;
@@ -226,7 +232,7 @@ struct RootWalk {
 
     __device__ WalkResult count(uint64_t s, uint64_t end) const {
         const uint32_t D = t.root_depth;
-        if (s + D > end) return WalkResult{0, 0, 0};
+        if (s + D > end) return WalkResult{0, 0, 0, 0};
         uint64_t w8 = 0;
 #pragma unroll
         for (int i = 0; i < 8; i++)
@@ -234,23 +240,27 @@ struct RootWalk {
         uint32_t key = 0;
         for (uint32_t i = 0; i < D; i++) {
             const uint32_t c = (uint32_t)(w8 >> (8 * i)) & 0xffu;
-            if (PACK2 && c > 3) return WalkResult{0, 0, 0};  // a byte outside the 2-bit codes
+            if (PACK2 && c > 3) return WalkResult{0, 0, 0, 0};  // a byte outside the 2-bit codes
             key = (key << (PACK2 ? 2 : 8)) | c;
         }
         const uint32_t wi = key >> 5, b = key & 31;
         const uint32_t word = img[kLdsRoot + wi];
-        if (!((word >> b) & 1u)) return WalkResult{0, 0, 0};
+        if (!((word >> b) & 1u)) return WalkResult{0, 0, 0, 0};
         const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + kLdsRank);
         uint32_t q = t.root_base + rank[wi] + __builtin_popcount(word & ((1u << b) - 1u));
         // continue with the bytes already loaded, then one load per level
         const Trie<LAYOUT> T{t};
-        WalkResult r{0, 0, 0};
+        WalkResult r{0, 0, 0, 0};
         uint64_t i = s + D;
         for (;;) {
             const uint4 tl = T.tail(q);
             if (T.is_term(q)) {
-                r.cnt += T.ids(q);
-                r.term0 = r.nterm == 0 ? q : r.term0;
+                const uint32_t f = t.out_first[q], k = t.out_first[q + 1] - f;
+                r.cnt += k;
+                if (r.nterm == 0) {
+                    r.f0 = f;
+                    r.k0 = k;
+                }
                 r.nterm++;
             }
             if (i >= end) break;
@@ -474,7 +484,7 @@ struct Scanner {
         const bool on = lane < cnt;
         const uint32_t sl = on ? q[first + lane] : 0u;
         const uint64_t s = S.a + sl;
-        WalkResult r{0, 0, 0};
+        WalkResult r{0, 0, 0, 0};
         if (on) r = W.count(s, end_of(s));
         S.my_cnt += r.cnt;
         const uint64_t hb = __ballot(r.cnt > 0);
@@ -483,8 +493,9 @@ struct Scanner {
             const uint32_t hcap = 1u << so.rec_log2;
             const bool store = r.cnt > 0 && S.nh + rank < hcap;
             if (store) {
-                const uint32_t nt = r.nterm < 0xffffu ? r.nterm : 0xffffu;
-                so.rec[((size_t)S.span << so.rec_log2) + S.nh + rank] = ((uint64_t)r.term0 << 32) | (nt << 16) | sl;
+                // ids of a single terminal go straight to the placement; 0: walk again
+                const uint32_t k = r.nterm == 1 && r.k0 < 0xffffu ? r.k0 : 0u;
+                so.rec[((size_t)S.span << so.rec_log2) + S.nh + rank] = ((uint64_t)r.f0 << 32) | (k << 16) | sl;
             }
             const uint64_t lost = __ballot(r.cnt > 0 && !store);
             if (lost) S.ovf = __builtin_amdgcn_readlane(sl, (int)__builtin_ctzll(lost));
@@ -721,6 +732,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
     __shared__ uint32_t span_nh[kBlockSpans];
     __shared__ uint32_t span_cls[kBlockSpans];  // 0: no match, 1: one lane writes it, 2: a wave does
     __shared__ uint32_t sh[4];
+    __shared__ uint64_t pre[kPlaceWaves];
     if (sizes) {
         n = sizes[0] < n ? sizes[0] : n;
         n_packets = sizes[1] < n_packets ? (uint32_t)sizes[1] : n_packets;
@@ -728,6 +740,12 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
     const uint64_t span_len = 1ull << span_log2;
     const uint32_t n_spans = (uint32_t)((n + span_len - 1) >> span_log2);
     const uint32_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
+    // Up to kDirectMaxSpans spans, each block sums the counts of all spans before it
+    // itself: no block waits on another, so blocks go by workgroup index, with no ticket,
+    // look-back or last-workgroup step; the last block writes the count. Beyond that,
+    // blocks are taken by ticket and placed by decoupled look-back.
+    const bool direct = n_spans <= kDirectMaxSpans;
+    uint32_t next_blk = blockIdx.x;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const Trie<LAYOUT> T{t};
     if (threadIdx.x == 0) sh[1] = __hip_atomic_load(&ts.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -740,17 +758,43 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
         return e < n ? e : n;
     };
     for (;;) {
-        if (threadIdx.x == 0) sh[0] = __hip_atomic_fetch_add(&ts.ctrl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const uint32_t blk = sh[0];
-        __syncthreads();  // sh[0] is rewritten by the next take
+        uint32_t blk;
+        if (direct) {
+            blk = next_blk;
+            next_blk += gridDim.x;
+        } else {
+            if (threadIdx.x == 0) sh[0] = __hip_atomic_fetch_add(&ts.ctrl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            blk = sh[0];
+            __syncthreads();  // sh[0] is rewritten by the next take
+        }
         if (blk >= n_blocks) break;
+        // wave 0, lane i: span i of the block; its count, record count, overflow and first
+        // records, all loaded at once (records past the stored ones are read and ignored)
+        const uint32_t my_sp = blk * kBlockSpans + lane;
+        const bool my_in = wave == 0 && my_sp < n_spans;
+        const uint64_t my_c = my_in ? so.cnt[my_sp] : 0;
+        const uint32_t my_nh = my_in ? so.nh[my_sp] : 0, my_ovf = my_in ? so.ovf[my_sp] : kNone;
+        uint64_t my_rec[kFastRecs];
+#pragma unroll
+        for (uint32_t k = 0; k < kFastRecs; k++) my_rec[k] = my_in ? so.rec[((size_t)my_sp << so.rec_log2) + k] : 0;
+        uint64_t before = 0;  // matches in spans before this block (direct mode)
+        if (direct) {
+            uint64_t part = 0;
+            const uint32_t lim_s = blk * kBlockSpans;
+#pragma unroll 8
+            for (uint32_t s = threadIdx.x; s < lim_s; s += kPlaceThreads) part += so.cnt[s];
+            part = wave_sum64(part);
+            if (lane == 0) pre[wave] = part;
+            __syncthreads();
+#pragma unroll
+            for (uint32_t w = 0; w < kPlaceWaves; w++) before += pre[w];
+            __syncthreads();  // pre[] is rewritten by the next block
+        }
         if (wave == 0) {
             // the block's span counts, their prefix, and the block's place by look-back
-            const uint32_t sp = blk * kBlockSpans + lane;
-            const bool in = sp < n_spans;
-            const uint64_t c = in ? so.cnt[sp] : 0;
-            const uint32_t nh = in ? so.nh[sp] : 0, ovf = in ? so.ovf[sp] : kNone;
+            const uint64_t c = my_c;
+            const uint32_t nh = my_nh, ovf = my_ovf;
             span_nh[lane] = nh;
             span_cls[lane] = c == 0 ? 0u : (ovf == kNone && nh <= kFastRecs) ? 1u : 2u;
             uint64_t inc = c;
@@ -760,13 +804,14 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                 if (lane >= (uint32_t)d) inc += u;
             }
             const uint64_t total = __shfl(inc, 63, 64);
-            if (lane == 0) {
+            if (direct && lane == 0 && blk == n_blocks - 1) *d_count = before + total;
+            if (!direct && lane == 0) {
                 const uint64_t v = total > kValueMask ? kValueMask : total;
                 __hip_atomic_store(&ts.word[blk], tagE | ((blk == 0 ? kFlagInc : kFlagAgg) << 42) | v,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            uint64_t excl = 0;
-            if (blk > 0) {
+            uint64_t excl = before;
+            if (!direct && blk > 0) {
                 int64_t j = (int64_t)blk - 1;
                 const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
                 for (;;) {
@@ -812,23 +857,18 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             // spans with a few records and no overflow: one lane each, all records'
             // loads in flight at once
             if (span_cls[lane] == 1) {
-                const uint32_t sp = blk * kBlockSpans + lane;
-                const uint64_t a = (uint64_t)sp << span_log2;
-                const uint32_t nh = span_nh[lane];
+                const uint64_t a = (uint64_t)my_sp << span_log2;
+                const uint32_t nh = my_nh;
                 uint64_t o = span_off[lane];
-                uint64_t rec[kFastRecs];
-#pragma unroll
-                for (uint32_t k = 0; k < kFastRecs; k++) rec[k] = k < nh ? so.rec[((size_t)sp << so.rec_log2) + k] : 0;
 #pragma unroll
                 for (uint32_t k = 0; k < kFastRecs; k++) {
                     if (k >= nh) break;
-                    const uint64_t s = a + (rec[k] & 0xffffu);
-                    const uint32_t nterm = (uint32_t)(rec[k] >> 16) & 0xffffu, q0 = (uint32_t)(rec[k] >> 32);
-                    if (nterm == 1) {
-                        const uint32_t f = t.out_first[q0], e = t.out_first[q0 + 1];
-                        if (o + (e - f) <= cap)
-                            for (uint32_t x = f; x < e; x++) keys[o + (x - f)] = (s << 32) | t.out_ids[x];
-                        o += e - f;
+                    const uint64_t s = a + (my_rec[k] & 0xffffu);
+                    const uint32_t ki = (uint32_t)(my_rec[k] >> 16) & 0xffffu, f = (uint32_t)(my_rec[k] >> 32);
+                    if (ki) {  // one terminal: its ids, in order
+                        if (o + ki <= cap)
+                            for (uint32_t x = 0; x < ki; x++) keys[o + x] = (s << 32) | t.out_ids[f + x];
+                        o += ki;
                     } else {
                         const uint64_t end = end_of(s);
                         const uint32_t c = T.walk_from(0, text, s, end).cnt;
@@ -852,7 +892,6 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             // latencies per 256 records rather than per 64
             for (uint32_t h0 = 0; h0 < nh; h0 += 64 * kRecRounds) {
                 uint64_t rec[kRecRounds];
-                uint32_t f[kRecRounds], e[kRecRounds];
 #pragma unroll
                 for (uint32_t u = 0; u < kRecRounds; u++) {
                     const uint32_t h = h0 + 64 * u + lane;
@@ -860,29 +899,22 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < kRecRounds; u++) {
-                    const uint32_t q0 = (uint32_t)(rec[u] >> 32);
-                    const bool one = h0 + 64 * u + lane < nh && ((rec[u] >> 16) & 0xffffu) == 1;
-                    f[u] = one ? t.out_first[q0] : 0u;
-                    e[u] = one ? t.out_first[q0 + 1] : 0u;
-                }
-#pragma unroll
-                for (uint32_t u = 0; u < kRecRounds; u++) {
                     if (h0 + 64 * u >= nh) break;  // wave-uniform
                     const bool on = h0 + 64 * u + lane < nh;
                     const uint64_t s = a + (rec[u] & 0xffffu);
-                    const uint32_t nterm = (uint32_t)(rec[u] >> 16) & 0xffffu;
+                    const uint32_t ki = (uint32_t)(rec[u] >> 16) & 0xffffu, f = (uint32_t)(rec[u] >> 32);
                     uint64_t end = 0;
-                    uint32_t c = e[u] - f[u];
-                    if (on && nterm != 1) {  // several terminals: walk again from the root
+                    uint32_t c = on ? ki : 0u;
+                    if (on && ki == 0) {  // several terminals: walk again from the root
                         end = end_of(s);
                         c = T.walk_from(0, text, s, end).cnt;
                     }
                     const uint32_t incl = wave_incl_scan(c);
                     const uint64_t o = run + incl - c;
                     if (c && o + c <= cap) {
-                        if (nterm == 1) {
+                        if (ki) {
                             const uint64_t hi = s << 32;
-                            for (uint32_t x = 0; x < c; x++) keys[o + x] = hi | t.out_ids[f[u] + x];
+                            for (uint32_t x = 0; x < c; x++) keys[o + x] = hi | t.out_ids[f + x];
                         } else {
                             T.emit_walk(text, s, end, keys, o, c);
                         }
@@ -908,6 +940,10 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             }
         }
         __syncthreads();  // span_off is rewritten by the next block
+    }
+    if (direct) {
+        if (n_blocks == 0 && blockIdx.x == 0 && threadIdx.x == 0) *d_count = 0;
+        return;
     }
     // last workgroup out: writes the count, resets the ticket, advances the epoch
     if (threadIdx.x == 0) {

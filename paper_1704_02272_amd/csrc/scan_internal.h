@@ -46,6 +46,7 @@ constexpr uint32_t kQCap = PFAC_QCAP;  // survivor queue; walked when a step mig
 constexpr uint32_t kHCapMinLog2 = 8; // match records kept per span: span / 64, at least 256
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
 constexpr uint32_t kFastRecs = 8;    // a span with at most this many records is written by one lane
+constexpr uint32_t kDirectMaxSpans = 16384;  // placement without look-back up to this many spans
 constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement wave issues together
 constexpr uint32_t kPlaceThreads = 256;
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
@@ -76,8 +77,10 @@ constexpr uint32_t kLdsWords = kLdsQueues + kWaves * kWaveLds / 4;
 // Per-span results of the count kernel (device memory, owned by a workspace).
 //   cnt[s]   matches in span s          nh[s]   records stored for span s
 //   ovf[s]   span-local start of the first matching start without a record, or ~0
-//   rec[(s << rec_log2) + i]   record i: first terminal node (bits 32..63) | terminals passed
-//                        (16..31, saturated) | span-local start (0..15)
+//   rec[(s << rec_log2) + i]   record i of a matching start: bits 32..63 = index in out_ids
+//                        of its first terminal's ids, bits 16..31 = how many (0 when it
+//                        passed several terminals or 65,535+ ids: the placement walks it
+//                        again), bits 0..15 = span-local start
 struct SpanOut {
     uint64_t *cnt;
     uint32_t *nh;

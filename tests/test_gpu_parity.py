@@ -134,8 +134,17 @@ def test_printable_256mib_full_and_repeatable():
     t = torch.from_numpy(w.text).to(DEV)
     got1 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
     got2 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    # 4 KiB spans: 65,536 spans, past the direct-prefix limit, so the placement takes
+    # blocks by ticket and finds their offsets by decoupled look-back
+    pfac.pfac_set_tuning(a, span_log2=12)
+    got4 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    got5 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    pfac.pfac_set_tuning(a)  # and back to direct placement on the same workspace
+    got6 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    assert np.array_equal(got6, want)
     pfac.pfac_set_tuning(a, algo="plain")
     got3 = pfac.keys_to_numpy(pfac.pfac_scan(a, t))
+    assert np.array_equal(got4, want) and np.array_equal(got5, want)
     assert np.array_equal(got3, want)
     assert np.array_equal(got1, want)
     assert np.array_equal(got2, want)
