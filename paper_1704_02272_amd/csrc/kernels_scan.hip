@@ -80,9 +80,9 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 // ------------------------------------------------------------------------ the walk
 // Result of one walk: how many pattern ids it passed, how many terminals, the first one.
 // A walk's pattern-id count, the number of terminals it passed, and the ids of the first
-// one: out_ids[f0 .. f0 + k0).
+// one: out_ids[f0 .. f0 + k0) (id0 = out_ids[f0] when k0 == 1).
 struct WalkResult {
-    uint32_t cnt, nterm, f0, k0;
+    uint32_t cnt, nterm, f0, k0, id0, q0, d0;  // q0, d0: node and depth of the first terminal
 };
 
 template <int LAYOUT>
@@ -171,7 +171,7 @@ struct Trie {
     // Walk from node q at text position i (end exclusive): count ids of every terminal,
     // including q itself.
     __device__ WalkResult walk_from(uint32_t q, const uint8_t *__restrict__ text, uint64_t i, uint64_t end) const {
-        WalkResult r{0, 0, 0, 0};
+        WalkResult r{0, 0, 0, 0, 0, 0, 0};
         for (;;) {
             const uint4 tl = tail(q);
             if (is_term(q)) {
@@ -193,10 +193,10 @@ struct Trie {
     // id; cnt is the walk's id count. Ids of one terminal are sorted; those of nested
     // terminals are merged by insertion.
     __device__ void emit_walk(const uint8_t *__restrict__ text, uint64_t s, uint64_t end, uint64_t *keys,
-                              uint64_t o, uint32_t cnt) const {
+                              uint64_t o, uint32_t cnt, uint32_t q = 0, uint64_t i0 = ~0ull) const {
         const uint64_t hi = s << 32;
-        uint32_t q = 0, k = 0, nterm = 0;
-        uint64_t i = s;
+        uint32_t k = 0, nterm = 0;
+        uint64_t i = i0 == ~0ull ? s : i0;
         for (;;) {
             const uint4 tl = tail(q);
             if (is_term(q)) {
@@ -232,7 +232,7 @@ struct RootWalk {
 
     __device__ WalkResult count(uint64_t s, uint64_t end) const {
         const uint32_t D = t.root_depth;
-        if (s + D > end) return WalkResult{0, 0, 0, 0};
+        if (s + D > end) return WalkResult{0, 0, 0, 0, 0, 0, 0};
         uint64_t w8 = 0;
 #pragma unroll
         for (int i = 0; i < 8; i++)
@@ -240,17 +240,17 @@ struct RootWalk {
         uint32_t key = 0;
         for (uint32_t i = 0; i < D; i++) {
             const uint32_t c = (uint32_t)(w8 >> (8 * i)) & 0xffu;
-            if (PACK2 && c > 3) return WalkResult{0, 0, 0, 0};  // a byte outside the 2-bit codes
+            if (PACK2 && c > 3) return WalkResult{0, 0, 0, 0, 0, 0, 0};  // a byte outside the 2-bit codes
             key = (key << (PACK2 ? 2 : 8)) | c;
         }
         const uint32_t wi = key >> 5, b = key & 31;
         const uint32_t word = img[kLdsRoot + wi];
-        if (!((word >> b) & 1u)) return WalkResult{0, 0, 0, 0};
+        if (!((word >> b) & 1u)) return WalkResult{0, 0, 0, 0, 0, 0, 0};
         const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + kLdsRank);
         uint32_t q = t.root_base + rank[wi] + __builtin_popcount(word & ((1u << b) - 1u));
         // continue with the bytes already loaded, then one load per level
         const Trie<LAYOUT> T{t};
-        WalkResult r{0, 0, 0, 0};
+        WalkResult r{0, 0, 0, 0, 0, 0, 0};
         uint64_t i = s + D;
         for (;;) {
             const uint4 tl = T.tail(q);
@@ -260,6 +260,9 @@ struct RootWalk {
                 if (r.nterm == 0) {
                     r.f0 = f;
                     r.k0 = k;
+                    r.id0 = t.out_ids[f];  // used only when k == 1; overlaps the rest of the walk
+                    r.q0 = q;
+                    r.d0 = (uint32_t)(i - s);
                 }
                 r.nterm++;
             }
@@ -484,7 +487,7 @@ struct Scanner {
         const bool on = lane < cnt;
         const uint32_t sl = on ? q[first + lane] : 0u;
         const uint64_t s = S.a + sl;
-        WalkResult r{0, 0, 0, 0};
+        WalkResult r{0, 0, 0, 0, 0, 0, 0};
         if (on) r = W.count(s, end_of(s));
         S.my_cnt += r.cnt;
         const uint64_t hb = __ballot(r.cnt > 0);
@@ -493,9 +496,20 @@ struct Scanner {
             const uint32_t hcap = 1u << so.rec_log2;
             const bool store = r.cnt > 0 && S.nh + rank < hcap;
             if (store) {
-                // ids of a single terminal go straight to the placement; 0: walk again
-                const uint32_t k = r.nterm == 1 && r.k0 < 0xffffu ? r.k0 : 0u;
-                so.rec[((size_t)S.span << so.rec_log2) + S.nh + rank] = ((uint64_t)r.f0 << 32) | (k << 16) | sl;
+                // one terminal: its id itself when it has one, else where its ids are;
+                // several: the first one's node and depth, where the placement resumes
+                uint32_t k, hi;
+                if (r.nterm == 1 && r.k0 < kRecMulti) {
+                    k = r.k0;
+                    hi = k == 1 ? r.id0 : r.f0;
+                } else if (r.nterm > 1 && r.d0 < kRecMulti - 1) {
+                    k = kRecMulti | r.d0;
+                    hi = r.q0;
+                } else {
+                    k = 0;  // walk again from the root
+                    hi = 0;
+                }
+                so.rec[((size_t)S.span << so.rec_log2) + S.nh + rank] = ((uint64_t)hi << 32) | (k << 16) | sl;
             }
             const uint64_t lost = __ballot(r.cnt > 0 && !store);
             if (lost) S.ovf = __builtin_amdgcn_readlane(sl, (int)__builtin_ctzll(lost));
@@ -865,14 +879,19 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                     if (k >= nh) break;
                     const uint64_t s = a + (my_rec[k] & 0xffffu);
                     const uint32_t ki = (uint32_t)(my_rec[k] >> 16) & 0xffffu, f = (uint32_t)(my_rec[k] >> 32);
-                    if (ki) {  // one terminal: its ids, in order
+                    if (ki == 1) {  // one terminal with one id: the record holds the id
+                        if (o + 1 <= cap) keys[o] = (s << 32) | f;
+                        o += 1;
+                    } else if (ki && ki < kRecMulti) {  // one terminal: its ids, in order
                         if (o + ki <= cap)
                             for (uint32_t x = 0; x < ki; x++) keys[o + x] = (s << 32) | t.out_ids[f + x];
                         o += ki;
-                    } else {
+                    } else {  // several terminals: walk again from the first one (or the root)
                         const uint64_t end = end_of(s);
-                        const uint32_t c = T.walk_from(0, text, s, end).cnt;
-                        if (c && o + c <= cap) T.emit_walk(text, s, end, keys, o, c);
+                        const uint32_t q0 = ki ? f : 0u;
+                        const uint64_t i0 = s + (ki ? (ki & (kRecMulti - 1)) : 0u);
+                        const uint32_t c = T.walk_from(q0, text, i0, end).cnt;
+                        if (c && o + c <= cap) T.emit_walk(text, s, end, keys, o, c, q0, i0);
                         o += c;
                     }
                 }
@@ -904,19 +923,24 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
                     const uint64_t s = a + (rec[u] & 0xffffu);
                     const uint32_t ki = (uint32_t)(rec[u] >> 16) & 0xffffu, f = (uint32_t)(rec[u] >> 32);
                     uint64_t end = 0;
+                    const bool multi = ki == 0 || ki >= kRecMulti;
+                    const uint32_t q0 = ki ? f : 0u;
+                    const uint64_t i0 = s + (ki ? (ki & (kRecMulti - 1)) : 0u);
                     uint32_t c = on ? ki : 0u;
-                    if (on && ki == 0) {  // several terminals: walk again from the root
+                    if (on && multi) {  // several terminals: walk again from the first one (or the root)
                         end = end_of(s);
-                        c = T.walk_from(0, text, s, end).cnt;
+                        c = T.walk_from(q0, text, i0, end).cnt;
                     }
                     const uint32_t incl = wave_incl_scan(c);
                     const uint64_t o = run + incl - c;
                     if (c && o + c <= cap) {
-                        if (ki) {
+                        if (ki == 1) {
+                            keys[o] = (s << 32) | f;
+                        } else if (!multi) {
                             const uint64_t hi = s << 32;
                             for (uint32_t x = 0; x < c; x++) keys[o + x] = hi | t.out_ids[f + x];
                         } else {
-                            T.emit_walk(text, s, end, keys, o, c);
+                            T.emit_walk(text, s, end, keys, o, c, q0, i0);
                         }
                     }
                     run += __builtin_amdgcn_readlane(incl, 63);

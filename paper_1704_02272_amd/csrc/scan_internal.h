@@ -45,6 +45,7 @@ static_assert(PFAC_PREFETCH >= 2, "the next step's first word comes from the pre
 constexpr uint32_t kQCap = PFAC_QCAP;  // survivor queue; walked when a step might not fit, and at the span end
 constexpr uint32_t kHCapMinLog2 = 8; // match records kept per span: span / 64, at least 256
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
+constexpr uint32_t kRecMulti = 0x8000;  // record flag: several terminals (see SpanOut)
 constexpr uint32_t kFastRecs = 8;    // a span with at most this many records is written by one lane
 constexpr uint32_t kDirectMaxSpans = 16384;  // placement without look-back up to this many spans
 constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement wave issues together
@@ -77,10 +78,13 @@ constexpr uint32_t kLdsWords = kLdsQueues + kWaves * kWaveLds / 4;
 // Per-span results of the count kernel (device memory, owned by a workspace).
 //   cnt[s]   matches in span s          nh[s]   records stored for span s
 //   ovf[s]   span-local start of the first matching start without a record, or ~0
-//   rec[(s << rec_log2) + i]   record i of a matching start: bits 32..63 = index in out_ids
-//                        of its first terminal's ids, bits 16..31 = how many (0 when it
-//                        passed several terminals or 65,535+ ids: the placement walks it
-//                        again), bits 0..15 = span-local start
+//   rec[(s << rec_log2) + i]   record i of a matching start, bits 0..15 = span-local start,
+//                        bits 16..31 = F, bits 32..63 = H:
+//                        F in 1 .. kRecMulti-1: one terminal with F ids; H = the id itself
+//                          when F == 1, else the index of the ids in out_ids;
+//                        F = kRecMulti | d: several terminals, the first one node H at depth
+//                          d: the placement walks again from there;
+//                        F = 0: walk again from the root (ids or depths past the fields)
 struct SpanOut {
     uint64_t *cnt;
     uint32_t *nh;
