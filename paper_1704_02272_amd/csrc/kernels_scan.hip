@@ -365,13 +365,18 @@ __device__ __forceinline__ uint32_t probe_root(const uint32_t *root, uint32_t ke
 // Survivor mask of this lane's 16 starts (bit j = start 16*lane + j of the step).
 // cur: this lane's 16 bytes; next_d0: the 4 bytes after them; c0/c1: two-bit codes of
 // this lane's and the next 16 bytes.
-template <bool PACK2>
+// Prefilter forms, fixed per kernel instance: FM_K4 four-byte keys and no pattern shorter
+// than four; FM_GEN any key length, with the short-pattern bitmap; FM_ROOT no hashed
+// filter (the root image's D-gram bitmap is the test).
+enum FilterMode : int { FM_K4 = 0, FM_GEN = 1, FM_ROOT = 2 };
+
+template <bool PACK2, int FM>
 __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_t *img, uint4 cur,
                                                 uint32_t next_d0, uint32_t c0, uint32_t c1) {
     uint32_t mask = 0;
     if (!PACK2) {
         const uint32_t d[5] = {cur.x, cur.y, cur.z, cur.w, next_d0};
-        if (t.filter_k == 4 && !t.has_short) {
+        if (FM == FM_K4) {
             // one chain of shift-or steps, start 15 first, so each start costs one insert
 #pragma unroll
             for (int j = 15; j >= 0; j--) {
@@ -384,7 +389,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
                 rem &= rem - 1;
                 mask &= ~((probe2(img, bytes4_at(cur, next_d0, j)) ^ 1u) << j);
             }
-        } else if (t.filter_k) {
+        } else if (FM == FM_GEN) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
             const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : (1u << (8 * t.filter_k)) - 1u;
             const uint32_t *shrt = img + kLdsShort;
@@ -419,9 +424,9 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         }
     } else {
         // window of K symbols at j: the top 2K bits of symbols j..j+15
-        const uint32_t K = t.filter_k ? t.filter_k : t.root_depth;
+        const uint32_t K = FM != FM_ROOT ? t.filter_k : t.root_depth;
         const uint32_t rs = 32 - 2 * K;
-        if (t.filter_k) {
+        if (FM != FM_ROOT) {
             // k-gram filter, plus the short bitmap (D-grams) for patterns shorter than k
             const uint32_t *shrt = img + kLdsShort;
             const uint32_t rsd = 32 - 2 * t.root_depth;
@@ -463,7 +468,7 @@ struct SpanState {
     uint64_t my_cnt;  // this lane's share of the span's match count
 };
 
-template <int LAYOUT, bool PACK2, bool SEG>
+template <int LAYOUT, bool PACK2, bool SEG, int FM>
 struct Scanner {
     const DevTable &t;
     RootWalk<LAYOUT, PACK2> W;
@@ -604,7 +609,7 @@ struct Scanner {
             const uint32_t nd = lasth ? next_d0 : cur.v[h + 1].x;
             const uint32_t c0 = PACK2 ? pack2x16(cur.v[h]) : 0u;
             const uint32_t c1 = PACK2 ? (lasth ? next_c : pack2x16(cur.v[h + 1])) : 0u;
-            m |= prefilter16<PACK2>(t, W.img, cur.v[h], nd, c0, c1) << (16 * h);
+            m |= prefilter16<PACK2, FM>(t, W.img, cur.v[h], nd, c0, c1) << (16 * h);
         }
         const uint32_t sl0 = (uint32_t)(step - S.a) + kLaneBytes * lane;  // span-local start of bit 0
         if (step + kStep > top) {  // last step: keep starts below top
@@ -689,7 +694,7 @@ struct Scanner {
 };
 
 // ------------------------------------------------------------------ count kernel
-template <int LAYOUT, bool PACK2, bool SEG>
+template <int LAYOUT, bool PACK2, bool SEG, int FM>
 __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
                                                       const uint64_t *__restrict__ offsets, uint32_t n_packets,
                                                       SpanOut so, const uint64_t *__restrict__ sizes,
@@ -716,7 +721,7 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     // load offsets) then stays in scalar registers
     const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint16_t *wq = reinterpret_cast<uint16_t *>(img + kLdsQueues) + wave * kQCap;
-    Scanner<LAYOUT, PACK2, SEG> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
+    Scanner<LAYOUT, PACK2, SEG, FM> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
                                    offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0};
     const uint32_t waves = gridDim.x * kWaves;
     for (uint32_t span = blockIdx.x * kWaves + wave; span < n_spans; span += waves) {
@@ -1005,13 +1010,13 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
     }
 }
 
-template <int LAYOUT, bool PACK2, bool SEG>
+template <int LAYOUT, bool PACK2, bool SEG, int FM>
 int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
                const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s) {
     const uint64_t n_spans = (n + (1ull << span_log2) - 1) >> span_log2;
     const uint64_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
-    auto kc = scan_count<LAYOUT, PACK2, SEG>;
+    auto kc = scan_count<LAYOUT, PACK2, SEG, FM>;
     auto kp = place_emit<LAYOUT, SEG>;
     static std::once_flag once;
     static int cus = 0, per_cu = 1, per_cu_p = 1;
@@ -1051,15 +1056,23 @@ int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint6
     const bool seg = offsets != nullptr;
     const bool narrow = t.layout == LAYOUT_NARROW;
     const bool pack2 = t.pack2 != 0;
-#define PFAC_L(LA, P2, SG) \
-    return launch_one<LA, P2, SG>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, span_log2, s)
+    const int fm = t.filter_k == 0 ? FM_ROOT : (!pack2 && t.filter_k == 4 && !t.has_short) ? FM_K4 : FM_GEN;
+#define PFAC_L(LA, P2, SG, F) \
+    return launch_one<LA, P2, SG, F>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, span_log2, s)
+#define PFAC_FM(LA, P2, SG)                                    \
+    do {                                                       \
+        if (fm == FM_ROOT) PFAC_L(LA, P2, SG, FM_ROOT);        \
+        if (fm == FM_GEN || P2) PFAC_L(LA, P2, SG, FM_GEN);    \
+        PFAC_L(LA, P2, SG, FM_K4);                             \
+    } while (0)
     if (narrow) {
-        if (pack2) { if (seg) PFAC_L(LAYOUT_NARROW, true, true); else PFAC_L(LAYOUT_NARROW, true, false); }
-        else { if (seg) PFAC_L(LAYOUT_NARROW, false, true); else PFAC_L(LAYOUT_NARROW, false, false); }
+        if (pack2) { if (seg) PFAC_FM(LAYOUT_NARROW, true, true); else PFAC_FM(LAYOUT_NARROW, true, false); }
+        else { if (seg) PFAC_FM(LAYOUT_NARROW, false, true); else PFAC_FM(LAYOUT_NARROW, false, false); }
     } else {
-        if (seg) PFAC_L(LAYOUT_WIDE, false, true);
-        PFAC_L(LAYOUT_WIDE, false, false);
+        if (seg) PFAC_FM(LAYOUT_WIDE, false, true);
+        PFAC_FM(LAYOUT_WIDE, false, false);
     }
+#undef PFAC_FM
 #undef PFAC_L
 }
 
