@@ -53,7 +53,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     const uint32_t bits = t.pack2 ? 2 : 8;
     if (a->n_pats == 0) {
         t.root_depth = t.root_bits = t.root_base = 0;
-        t.filter_k = t.filter_log2 = t.has_short = 0;
+        t.filter_k = t.filter_log2 = t.has_short = t.sampled = 0;
         t.lds_words = t.root_word = t.rank_word = t.short_word = 0;
         a->lds_image.clear();
         return;
@@ -108,7 +108,9 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     t.filter_k = K > D ? K : 0;
     t.filter_log2 = flog2;
     t.has_short = any_short ? 1 : 0;
-    const uint32_t filter_words = flog2 ? kFilterWordsMax + kFilter2Words : 0;
+    // four-byte keys and no shorter pattern: the sampled layout
+    t.sampled = (!t.pack2 && t.filter_k == 4 && !any_short) ? 1u : 0u;
+    const uint32_t filter_words = flog2 ? kFilterRegionWords : 0;
     t.root_word = filter_words;
     t.rank_word = filter_words + root_words;
     t.short_word = t.rank_word + rank_words;
@@ -130,7 +132,16 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     }
     // every depth-D node is a D-prefix of some pattern (D <= shortest length)
     if (run != a->depth_start[D + 1] - a->depth_start[D]) throw std::bad_alloc();
-    for (uint32_t key : fkeys) filter_insert(img, key, kMaxFilterLog2, kFilter2Log2);
+    if (t.sampled) {
+        for (uint32_t key : fkeys) filter_insert(img, key, kLdsS1, kS1Words, kLdsS2, kS2Words);
+        for (uint32_t j = 0; j < a->n_pats; j++) {
+            const uint8_t *p = P[j];  // every pattern has four or more bytes here
+            filter3_insert(img, (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16), kFilterMul3, kS3Words);
+            filter3_insert(img, (uint32_t)p[1] | ((uint32_t)p[2] << 8) | ((uint32_t)p[3] << 16), kFilterMul3, kS3Words);
+        }
+    } else {
+        for (uint32_t key : fkeys) filter_insert(img, key, kLdsF1, kFilterWordsMax, 0, kFilter2Words);
+    }
 }
 
 }  // namespace

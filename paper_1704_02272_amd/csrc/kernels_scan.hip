@@ -349,6 +349,23 @@ __device__ __forceinline__ uint32_t probe2(const uint32_t *img, uint32_t key) {
     return (w >> (h >> 27)) & 1u;
 }
 
+// Sampled layout: the 3-gram probe (bytes j..j+2 of x, its top byte ignored by the
+// 24-bit multiply) and the two probes of a candidate start's 4-gram.
+__device__ __forceinline__ uint32_t probe3(const uint32_t *img, uint32_t x) {
+    const uint32_t h = (x & 0xffffffu) * kFilterMul3;  // low half of a 24 x 24-bit product
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) +
+                                                          ((h >> 16) & ((kS3Words - 1u) << 2)));
+    return __builtin_amdgcn_ubfe(w, x, 1);
+}
+__device__ __forceinline__ uint32_t probe4s(const uint32_t *img, uint32_t key) {
+    const uint32_t o1 = (__umulhi(key, kFilterMul) & ((kS1Words - 1u) << 2)) + kLdsS1 * 4;
+    const uint32_t w1 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o1);
+    const uint32_t h2 = __umulhi(key, kFilterMul2);
+    const uint32_t o2 = (h2 & ((kS2Words - 1u) << 2)) + kLdsS2 * 4;
+    const uint32_t w2 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o2);
+    return __builtin_amdgcn_ubfe(w1, key, 1) & (w2 >> (h2 >> 27));
+}
+
 // Four bytes starting at byte j (0..15) of the 20 bytes v, d4 (little-endian words).
 __device__ __forceinline__ uint32_t bytes4_at(uint4 v, uint32_t d4, uint32_t j) {
     const uint32_t qd = j >> 2;
@@ -366,8 +383,8 @@ __device__ __forceinline__ uint32_t probe_root(const uint32_t *root, uint32_t ke
 // cur: this lane's 16 bytes; next_d0: the 4 bytes after them; c0/c1: two-bit codes of
 // this lane's and the next 16 bytes.
 // Prefilter forms, fixed per kernel instance: FM_K4 four-byte keys and no pattern shorter
-// than four; FM_GEN any key length, with the short-pattern bitmap; FM_ROOT no hashed
-// filter (the root image's D-gram bitmap is the test).
+// than four (the sampled layout); FM_GEN any key length, with the short-pattern bitmap;
+// FM_ROOT no hashed filter (the root image's D-gram bitmap is the test).
 enum FilterMode : int { FM_K4 = 0, FM_GEN = 1, FM_ROOT = 2 };
 
 template <bool PACK2, int FM>
@@ -377,17 +394,25 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
     if (!PACK2) {
         const uint32_t d[5] = {cur.x, cur.y, cur.z, cur.w, next_d0};
         if (FM == FM_K4) {
-            // one chain of shift-or steps, start 15 first, so each start costs one insert
+            // sampled: probe the 3-gram at every odd start j; a pattern (four bytes or
+            // more) starting at j or j-1 puts its 3-gram at offset 0 or 1 there. Odd
+            // starts that pass stand for the two candidates j-1 and j, each then checked
+            // by its 4-gram against the two-probe filter.
+            uint32_t odd = 0;
 #pragma unroll
-            for (int j = 15; j >= 0; j--) {
-                const uint32_t x = (j & 3) ? __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3) : d[j >> 2];
-                mask = (mask << 1) | probe(img, x);
+            for (int j = 15; j >= 1; j -= 2) {
+                const uint32_t x = __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3);
+                odd |= probe3(img, x) << j;
             }
-            uint32_t rem = mask;
-            while (rem) {  // second probe of the few that passed
-                const uint32_t j = __builtin_ctz(rem);
-                rem &= rem - 1;
-                mask &= ~((probe2(img, bytes4_at(cur, next_d0, j)) ^ 1u) << j);
+            while (odd) {
+                const uint32_t j = __builtin_ctz(odd);
+                odd &= odd - 1;
+                const uint32_t qd = j >> 2;  // j - 1 and j share their words
+                const uint32_t lo = qd == 0 ? cur.x : qd == 1 ? cur.y : qd == 2 ? cur.z : cur.w;
+                const uint32_t hi = qd == 0 ? cur.y : qd == 1 ? cur.z : qd == 2 ? cur.w : next_d0;
+                const uint32_t k1 = __builtin_amdgcn_alignbyte(hi, lo, j & 3);
+                const uint32_t k0 = __builtin_amdgcn_alignbyte(hi, lo, (j - 1) & 3);
+                mask |= (probe4s(img, k0) << (j - 1)) | (probe4s(img, k1) << j);
             }
         } else if (FM == FM_GEN) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
@@ -1056,7 +1081,7 @@ int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint6
     const bool seg = offsets != nullptr;
     const bool narrow = t.layout == LAYOUT_NARROW;
     const bool pack2 = t.pack2 != 0;
-    const int fm = t.filter_k == 0 ? FM_ROOT : (!pack2 && t.filter_k == 4 && !t.has_short) ? FM_K4 : FM_GEN;
+    const int fm = t.filter_k == 0 ? FM_ROOT : t.sampled ? FM_K4 : FM_GEN;
 #define PFAC_L(LA, P2, SG, F) \
     return launch_one<LA, P2, SG, F>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, span_log2, s)
 #define PFAC_FM(LA, P2, SG)                                    \

@@ -66,6 +66,7 @@ struct DevTable {
     uint32_t filter_k;          // k (symbols per filter key); 0 = no hashed filter
     uint32_t has_short;         // 1: some pattern is shorter than k (short bitmap used)
     uint32_t filter_log2;       // log2(bits of the first-probe region); 0 = no filter
+    uint32_t sampled;           // 1: sampled prefilter layout (every second start probed)
     uint32_t lds_words;         // total image size in 32-bit words
     uint32_t root_word;         // word offset of the root bitmap
     uint32_t rank_word;         // word offset of the rank table
@@ -85,11 +86,19 @@ constexpr uint32_t kFilterMul2 = 0x85EBCA6Bu; // second hash (MurmurHash3 finali
 __host__ __device__ inline uint32_t filter_hi(uint32_t key, uint32_t mul) {
     return (uint32_t)(((uint64_t)key * mul) >> 32);
 }
-inline void filter_insert(uint32_t *F, uint32_t key, uint32_t log2_a, uint32_t log2_b) {
-    const uint32_t wa = 1u << (log2_a - 5), wb = 1u << (log2_b - 5);
-    F[wb + ((filter_hi(key, kFilterMul) >> 2) & (wa - 1u))] |= 1u << (key & 31);
+// Insert key into a two-probe filter whose first-probe part (wa words) starts at word
+// oa of F and whose second-probe part (wb words) starts at word ob.
+inline void filter_insert(uint32_t *F, uint32_t key, uint32_t oa, uint32_t wa, uint32_t ob, uint32_t wb) {
+    F[oa + ((filter_hi(key, kFilterMul) >> 2) & (wa - 1u))] |= 1u << (key & 31);
     const uint32_t h2 = filter_hi(key, kFilterMul2);
-    F[(h2 >> 2) & (wb - 1u)] |= 1u << (h2 >> 27);
+    F[ob + ((h2 >> 2) & (wb - 1u))] |= 1u << (h2 >> 27);
+}
+
+// 3-gram key (three bytes, first one lowest) of the sampled prefilter: the word from the
+// top bits of the low 32 bits of key * mul3 (both 24-bit), bit = key & 31.
+inline void filter3_insert(uint32_t *F, uint32_t key, uint32_t mul3, uint32_t words) {
+    const uint32_t h = (uint32_t)((uint64_t)(key & 0xffffffu) * (mul3 & 0xffffffu));
+    F[(h >> 18) & (words - 1u)] |= 1u << (key & 31);
 }
 
 struct Workspace;  // per (device, stream) scratch, defined in the runtime

@@ -55,21 +55,36 @@ constexpr uint32_t kWaveLds = kQCap * 2;  // bytes of LDS per wave (survivor que
 static_assert(kWaveLds % 16 == 0, "wave regions stay 16-byte aligned");
 static_assert(kQCap >= 128, "a queue holds at least two walk batches");
 
-// Fixed LDS layout of the scan kernel (32-bit words): the prefilter's second-probe
-// region at offset 0, its first-probe region right after (its offset, 32 KiB, fits the
-// LDS instructions' immediate offset), then the root bitmap and its rank table, the
-// short-pattern bitmap and the per-wave queues. A probe's masked hash plus the region's
-// compile-time offset is its byte address.
-constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;    // first-probe region: 2^19 bits
-constexpr uint32_t kFilter2Log2 = PFAC_FILTER2_LOG2;     // second-probe region: 2^18 bits
+// Fixed LDS layout of the scan kernel (32-bit words): a 112 KiB prefilter region at
+// offset 0, then the root bitmap and its rank table, the short-pattern bitmap and the
+// per-wave queues. The prefilter region holds one of two layouts (a probe's masked hash
+// plus its part's compile-time offset is its byte address):
+//   general   [second-probe part: 2^18 bits][first-probe part: 2^19 bits]
+//             two-probe Bloom filter over k-gram keys, every start probed
+//   sampled   [3-gram part: 2^19 bits][second-probe part: 2^17 bits][first-probe part: 2^18 bits]
+//             patterns of four or more bytes and k = 4: only every second start is
+//             probed, with the 3-gram there against the 3-grams at offsets 0 and 1 of
+//             every pattern; the two starts it stands for are then checked against the
+//             two-probe Bloom filter over 4-grams.
+// The hot first probe's part sits below 64 KiB so its offset folds into the LDS
+// instruction.
+constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;    // general first-probe part: 2^19 bits
+constexpr uint32_t kFilter2Log2 = PFAC_FILTER2_LOG2;     // general second-probe part: 2^18 bits
 constexpr uint32_t kFilterWordsMax = 1u << (kMaxFilterLog2 - 5);
 constexpr uint32_t kFilter2Words = 1u << (kFilter2Log2 - 5);
-constexpr uint32_t kLdsF1 = kFilter2Words;                // word offset of the first-probe region
-constexpr uint32_t kAmask1 = (kFilterWordsMax - 1u) << 2; // byte-offset masks of the regions
+constexpr uint32_t kLdsF1 = kFilter2Words;                // word offset of the first-probe part
+constexpr uint32_t kAmask1 = (kFilterWordsMax - 1u) << 2; // byte-offset masks of the parts
 constexpr uint32_t kAmask2 = (kFilter2Words - 1u) << 2;
+constexpr uint32_t kS3Words = 1u << 14;                   // sampled: 3-gram part (64 KiB)
+constexpr uint32_t kS2Words = 1u << 12;                   // sampled: second-probe part (16 KiB)
+constexpr uint32_t kS1Words = 1u << 13;                   // sampled: first-probe part (32 KiB)
+constexpr uint32_t kLdsS2 = kS3Words, kLdsS1 = kS3Words + kS2Words;
+constexpr uint32_t kFilterRegionWords = kS3Words + kS2Words + kS1Words;
+static_assert(kFilterRegionWords >= kFilter2Words + kFilterWordsMax, "both layouts fit the region");
+constexpr uint32_t kFilterMul3 = 0x9E3779u;  // 24-bit multiplier of the 3-gram hash
 constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
-constexpr uint32_t kLdsRoot = kLdsF1 + kFilterWordsMax;
+constexpr uint32_t kLdsRoot = kFilterRegionWords;
 constexpr uint32_t kLdsRank = kLdsRoot + kRootWordsMax;
 constexpr uint32_t kLdsShort = kLdsRank + kRankWordsMax;
 constexpr uint32_t kLdsQueues = kLdsShort + kRootWordsMax;
