@@ -83,6 +83,7 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 // one: out_ids[f0 .. f0 + k0) (id0 = out_ids[f0] when k0 == 1).
 struct WalkResult {
     uint32_t cnt, nterm, f0, k0, id0, q0, d0;  // q0, d0: node and depth of the first terminal
+    uint32_t k1, id1;                          // second terminal: its id count, its id when one
 };
 
 template <int LAYOUT>
@@ -171,7 +172,7 @@ struct Trie {
     // Walk from node q at text position i (end exclusive): count ids of every terminal,
     // including q itself.
     __device__ WalkResult walk_from(uint32_t q, const uint8_t *__restrict__ text, uint64_t i, uint64_t end) const {
-        WalkResult r{0, 0, 0, 0, 0, 0, 0};
+        WalkResult r{0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (;;) {
             const uint4 tl = tail(q);
             if (is_term(q)) {
@@ -232,7 +233,7 @@ struct RootWalk {
 
     __device__ WalkResult count(uint64_t s, uint64_t end) const {
         const uint32_t D = t.root_depth;
-        if (s + D > end) return WalkResult{0, 0, 0, 0, 0, 0, 0};
+        if (s + D > end) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};
         uint64_t w8 = 0;
 #pragma unroll
         for (int i = 0; i < 8; i++)
@@ -240,17 +241,17 @@ struct RootWalk {
         uint32_t key = 0;
         for (uint32_t i = 0; i < D; i++) {
             const uint32_t c = (uint32_t)(w8 >> (8 * i)) & 0xffu;
-            if (PACK2 && c > 3) return WalkResult{0, 0, 0, 0, 0, 0, 0};  // a byte outside the 2-bit codes
+            if (PACK2 && c > 3) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};  // a byte outside the 2-bit codes
             key = (key << (PACK2 ? 2 : 8)) | c;
         }
         const uint32_t wi = key >> 5, b = key & 31;
         const uint32_t word = img[kLdsRoot + wi];
-        if (!((word >> b) & 1u)) return WalkResult{0, 0, 0, 0, 0, 0, 0};
+        if (!((word >> b) & 1u)) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};
         const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + kLdsRank);
         uint32_t q = t.root_base + rank[wi] + __builtin_popcount(word & ((1u << b) - 1u));
         // continue with the bytes already loaded, then one load per level
         const Trie<LAYOUT> T{t};
-        WalkResult r{0, 0, 0, 0, 0, 0, 0};
+        WalkResult r{0, 0, 0, 0, 0, 0, 0, 0, 0};
         uint64_t i = s + D;
         for (;;) {
             const uint4 tl = T.tail(q);
@@ -263,6 +264,9 @@ struct RootWalk {
                     r.id0 = t.out_ids[f];  // used only when k == 1; overlaps the rest of the walk
                     r.q0 = q;
                     r.d0 = (uint32_t)(i - s);
+                } else if (r.nterm == 1) {
+                    r.k1 = k;
+                    r.id1 = t.out_ids[f];
                 }
                 r.nterm++;
             }
@@ -517,34 +521,51 @@ struct Scanner {
         const bool on = lane < cnt;
         const uint32_t sl = on ? q[first + lane] : 0u;
         const uint64_t s = S.a + sl;
-        WalkResult r{0, 0, 0, 0, 0, 0, 0};
+        WalkResult r{0, 0, 0, 0, 0, 0, 0, 0, 0};
         if (on) r = W.count(s, end_of(s));
         S.my_cnt += r.cnt;
         const uint64_t hb = __ballot(r.cnt > 0);
         if (hb && S.ovf == kNone) {
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(hb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)hb, 0u));
+            // records per start: one; two (one per id, in id order) for a start that
+            // passed exactly two terminals with one id each
+            const bool two = r.nterm == 2 && r.k0 == 1 && r.k1 == 1;
+            const uint32_t rc = r.cnt > 0 ? (two ? 2u : 1u) : 0u;
+            const uint32_t incl = wave_incl_scan(rc);
+            const uint32_t pos = S.nh + incl - rc;
             const uint32_t hcap = 1u << so.rec_log2;
-            const bool store = r.cnt > 0 && S.nh + rank < hcap;
+            const bool store = rc > 0 && pos + rc <= hcap;
             if (store) {
-                // one terminal: its id itself when it has one, else where its ids are;
-                // several: the first one's node and depth, where the placement resumes
-                uint32_t k, hi;
-                if (r.nterm == 1 && r.k0 < kRecMulti) {
-                    k = r.k0;
-                    hi = k == 1 ? r.id0 : r.f0;
-                } else if (r.nterm > 1 && r.d0 < kRecMulti - 1) {
-                    k = kRecMulti | r.d0;
-                    hi = r.q0;
+                uint64_t *rec = so.rec + ((size_t)S.span << so.rec_log2) + pos;
+                if (two) {
+                    const uint32_t a = r.id0 < r.id1 ? r.id0 : r.id1, b = r.id0 < r.id1 ? r.id1 : r.id0;
+                    rec[0] = ((uint64_t)a << 32) | (1u << 16) | sl;
+                    rec[1] = ((uint64_t)b << 32) | (1u << 16) | sl;
                 } else {
-                    k = 0;  // walk again from the root
-                    hi = 0;
+                    // one terminal: its id itself when it has one, else where its ids are;
+                    // several: the first one's node and depth, where the placement resumes
+                    uint32_t k, hi;
+                    if (r.nterm == 1 && r.k0 < kRecMulti) {
+                        k = r.k0;
+                        hi = k == 1 ? r.id0 : r.f0;
+                    } else if (r.nterm > 1 && r.d0 < kRecMulti - 1) {
+                        k = kRecMulti | r.d0;
+                        hi = r.q0;
+                    } else {
+                        k = 0;  // walk again from the root
+                        hi = 0;
+                    }
+                    rec[0] = ((uint64_t)hi << 32) | (k << 16) | sl;
                 }
-                so.rec[((size_t)S.span << so.rec_log2) + S.nh + rank] = ((uint64_t)hi << 32) | (k << 16) | sl;
             }
-            const uint64_t lost = __ballot(r.cnt > 0 && !store);
-            if (lost) S.ovf = __builtin_amdgcn_readlane(sl, (int)__builtin_ctzll(lost));
-            const uint32_t nh = S.nh + (uint32_t)__builtin_popcountll(hb);
-            S.nh = nh < hcap ? nh : hcap;
+            const uint64_t lost = __ballot(rc > 0 && !store);
+            if (lost) {
+                // records end where the first start that did not fit would have begun
+                const int f = (int)__builtin_ctzll(lost);
+                S.ovf = __builtin_amdgcn_readlane(sl, f);
+                S.nh = __builtin_amdgcn_readlane(pos, f);
+            } else {
+                S.nh += __builtin_amdgcn_readlane(incl, 63);
+            }
         }
     }
 
