@@ -136,8 +136,8 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
         for (uint32_t key : fkeys) filter_insert(img, key, kLdsS1, kS1Words, kLdsS2, kS2Words);
         for (uint32_t j = 0; j < a->n_pats; j++) {
             const uint8_t *p = P[j];  // every pattern has four or more bytes here
-            filter3_insert(img, (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16), kFilterMul3, kS3Words);
-            filter3_insert(img, (uint32_t)p[1] | ((uint32_t)p[2] << 8) | ((uint32_t)p[3] << 16), kFilterMul3, kS3Words);
+            filter3_insert(img, (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16), kFilterMul3, kLdsS3, kS3Words);
+            filter3_insert(img, (uint32_t)p[1] | ((uint32_t)p[2] << 8) | ((uint32_t)p[3] << 16), kFilterMul3, kLdsS3, kS3Words);
         }
     } else {
         for (uint32_t key : fkeys) filter_insert(img, key, kLdsF1, kFilterWordsMax, 0, kFilter2Words);

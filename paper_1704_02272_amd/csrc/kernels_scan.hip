@@ -357,17 +357,20 @@ __device__ __forceinline__ uint32_t probe2(const uint32_t *img, uint32_t key) {
 // 24-bit multiply) and the two probes of a candidate start's 4-gram.
 __device__ __forceinline__ uint32_t probe3(const uint32_t *img, uint32_t x) {
     const uint32_t h = (x & 0xffffffu) * kFilterMul3;  // low half of a 24 x 24-bit product
-    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) +
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + kLdsS3 * 4 +
                                                           ((h >> 16) & ((kS3Words - 1u) << 2)));
     return __builtin_amdgcn_ubfe(w, x, 1);
 }
-__device__ __forceinline__ uint32_t probe4s(const uint32_t *img, uint32_t key) {
+__device__ __forceinline__ uint32_t probe4s_first(const uint32_t *img, uint32_t key) {
     const uint32_t o1 = (__umulhi(key, kFilterMul) & ((kS1Words - 1u) << 2)) + kLdsS1 * 4;
     const uint32_t w1 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o1);
+    return __builtin_amdgcn_ubfe(w1, key, 1);
+}
+__device__ __forceinline__ uint32_t probe4s_second(const uint32_t *img, uint32_t key) {
     const uint32_t h2 = __umulhi(key, kFilterMul2);
     const uint32_t o2 = (h2 & ((kS2Words - 1u) << 2)) + kLdsS2 * 4;
     const uint32_t w2 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o2);
-    return __builtin_amdgcn_ubfe(w1, key, 1) & (w2 >> (h2 >> 27));
+    return (w2 >> (h2 >> 27)) & 1u;
 }
 
 // Four bytes starting at byte j (0..15) of the 20 bytes v, d4 (little-endian words).
@@ -416,7 +419,12 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
                 const uint32_t hi = qd == 0 ? cur.y : qd == 1 ? cur.z : qd == 2 ? cur.w : next_d0;
                 const uint32_t k1 = __builtin_amdgcn_alignbyte(hi, lo, j & 3);
                 const uint32_t k0 = __builtin_amdgcn_alignbyte(hi, lo, (j - 1) & 3);
-                mask |= (probe4s(img, k0) << (j - 1)) | (probe4s(img, k1) << j);
+                uint32_t p0 = probe4s_first(img, k0), p1 = probe4s_first(img, k1);
+                if (p0 | p1) {  // few pass the first probe: the second only for them
+                    p0 &= probe4s_second(img, k0);
+                    p1 &= probe4s_second(img, k1);
+                }
+                mask |= (p0 << (j - 1)) | (p1 << j);
             }
         } else if (FM == FM_GEN) {
             // k-gram filter, plus the short bitmap for patterns shorter than k

@@ -96,9 +96,9 @@ inline void filter_insert(uint32_t *F, uint32_t key, uint32_t oa, uint32_t wa, u
 
 // 3-gram key (three bytes, first one lowest) of the sampled prefilter: the word from the
 // top bits of the low 32 bits of key * mul3 (both 24-bit), bit = key & 31.
-inline void filter3_insert(uint32_t *F, uint32_t key, uint32_t mul3, uint32_t words) {
+inline void filter3_insert(uint32_t *F, uint32_t key, uint32_t mul3, uint32_t off, uint32_t words) {
     const uint32_t h = (uint32_t)((uint64_t)(key & 0xffffffu) * (mul3 & 0xffffffu));
-    F[(h >> 18) & (words - 1u)] |= 1u << (key & 31);
+    F[off + ((h >> 18) & (words - 1u))] |= 1u << (key & 31);
 }
 
 struct Workspace;  // per (device, stream) scratch, defined in the runtime

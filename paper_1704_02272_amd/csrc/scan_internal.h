@@ -61,13 +61,12 @@ static_assert(kQCap >= 128, "a queue holds at least two walk batches");
 // plus its part's compile-time offset is its byte address):
 //   general   [second-probe part: 2^18 bits][first-probe part: 2^19 bits]
 //             two-probe Bloom filter over k-gram keys, every start probed
-//   sampled   [3-gram part: 2^19 bits][second-probe part: 2^17 bits][first-probe part: 2^18 bits]
+//   sampled   [second-probe part: 2^17 bits][first-probe part: 2^18 bits][3-gram part: 2^19 bits]
 //             patterns of four or more bytes and k = 4: only every second start is
 //             probed, with the 3-gram there against the 3-grams at offsets 0 and 1 of
 //             every pattern; the two starts it stands for are then checked against the
 //             two-probe Bloom filter over 4-grams.
-// The hot first probe's part sits below 64 KiB so its offset folds into the LDS
-// instruction.
+// Every part starts below 64 KiB, so its offset folds into the LDS instruction.
 constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;    // general first-probe part: 2^19 bits
 constexpr uint32_t kFilter2Log2 = PFAC_FILTER2_LOG2;     // general second-probe part: 2^18 bits
 constexpr uint32_t kFilterWordsMax = 1u << (kMaxFilterLog2 - 5);
@@ -78,7 +77,8 @@ constexpr uint32_t kAmask2 = (kFilter2Words - 1u) << 2;
 constexpr uint32_t kS3Words = 1u << 14;                   // sampled: 3-gram part (64 KiB)
 constexpr uint32_t kS2Words = 1u << 12;                   // sampled: second-probe part (16 KiB)
 constexpr uint32_t kS1Words = 1u << 13;                   // sampled: first-probe part (32 KiB)
-constexpr uint32_t kLdsS2 = kS3Words, kLdsS1 = kS3Words + kS2Words;
+constexpr uint32_t kLdsS2 = 0, kLdsS1 = kS2Words, kLdsS3 = kS2Words + kS1Words;
+static_assert(kLdsS3 * 4 < 65536, "the 3-gram part's offset fits the LDS instruction");
 constexpr uint32_t kFilterRegionWords = kS3Words + kS2Words + kS1Words;
 static_assert(kFilterRegionWords >= kFilter2Words + kFilterWordsMax, "both layouts fit the region");
 constexpr uint32_t kFilterMul3 = 0x9E3779u;  // 24-bit multiplier of the 3-gram hash
