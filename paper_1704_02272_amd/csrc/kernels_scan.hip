@@ -402,29 +402,13 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         const uint32_t d[5] = {cur.x, cur.y, cur.z, cur.w, next_d0};
         if (FM == FM_K4) {
             // sampled: probe the 3-gram at every odd start j; a pattern (four bytes or
-            // more) starting at j or j-1 puts its 3-gram at offset 0 or 1 there. Odd
-            // starts that pass stand for the two candidates j-1 and j, each then checked
-            // by its 4-gram against the two-probe filter.
-            uint32_t odd = 0;
+            // more) starting at j or j-1 puts its 3-gram at offset 0 or 1 there. The
+            // mask holds the odd starts that pass: candidates, each standing for the
+            // starts j-1 and j, which the wave then checks 64 at a time (check_batch).
 #pragma unroll
             for (int j = 15; j >= 1; j -= 2) {
                 const uint32_t x = __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3);
-                odd |= probe3(img, x) << j;
-            }
-            while (odd) {
-                const uint32_t j = __builtin_ctz(odd);
-                odd &= odd - 1;
-                const uint32_t qd = j >> 2;  // j - 1 and j share their words
-                const uint32_t lo = qd == 0 ? cur.x : qd == 1 ? cur.y : qd == 2 ? cur.z : cur.w;
-                const uint32_t hi = qd == 0 ? cur.y : qd == 1 ? cur.z : qd == 2 ? cur.w : next_d0;
-                const uint32_t k1 = __builtin_amdgcn_alignbyte(hi, lo, j & 3);
-                const uint32_t k0 = __builtin_amdgcn_alignbyte(hi, lo, (j - 1) & 3);
-                uint32_t p0 = probe4s_first(img, k0), p1 = probe4s_first(img, k1);
-                if (p0 | p1) {  // few pass the first probe: the second only for them
-                    p0 &= probe4s_second(img, k0);
-                    p1 &= probe4s_second(img, k1);
-                }
-                mask |= (p0 << (j - 1)) | (p1 << j);
+                mask |= probe3(img, x) << j;
             }
         } else if (FM == FM_GEN) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
@@ -503,6 +487,7 @@ struct SpanState {
     uint32_t nh;      // records stored
     uint32_t ovf;     // span-local start of the first matching start not recorded, or kNone
     uint64_t my_cnt;  // this lane's share of the span's match count
+    uint64_t top;     // starts at or past top are not counted here
 };
 
 template <int LAYOUT, bool PACK2, bool SEG, int FM>
@@ -515,7 +500,15 @@ struct Scanner {
     uint32_t n_packets;
     SpanOut so;
     uint16_t *q;  // survivor queue (span-local starts), kQCap entries
+    uint16_t *cq; // sampled prefilter: candidate list (step-local odd starts), kCCap entries
+    uint8_t *stg; // sampled prefilter: this wave's staged step (kStageBytes)
     bool aligned;
+
+    // A lane's bytes of one step: kLaneBytes (16 or 32) consecutive text bytes, with the
+    // two-bit codes of each 16 when symbols are two-bit codes.
+    struct Chunk {
+        uint4 v[kLaneBytes / 16];
+    };
 
     __device__ __forceinline__ uint64_t end_of(uint64_t s) const {
         if (!SEG) return n;
@@ -524,7 +517,7 @@ struct Scanner {
     }
 
     // Walk `cnt` queued survivors from q[first], one per lane; record the matching ones.
-    __device__ void walk_batch(SpanState &S, uint32_t first, uint32_t cnt) {
+    __device__ __forceinline__ void walk_batch(SpanState &S, uint32_t first, uint32_t cnt) {
         const uint32_t lane = lane_id();
         const bool on = lane < cnt;
         const uint32_t sl = on ? q[first + lane] : 0u;
@@ -578,7 +571,7 @@ struct Scanner {
     }
 
     // Walk every full batch of 64 queued survivors; keep the rest (< 64) at the front.
-    __device__ void drain(SpanState &S) {
+    __device__ __forceinline__ void drain(SpanState &S) {
         const uint32_t lane = lane_id();
         uint32_t done = 0;
         while (S.qlen - done >= 64) {
@@ -594,49 +587,137 @@ struct Scanner {
         S.qlen = rest;
     }
 
-    // Survivors of one step: append them to the queue in position order. Walks wait
-    // until the queue might not hold another step (or the span ends).
-    __device__ __forceinline__ void take(SpanState &S, uint32_t m, uint32_t sl0) {
+    // Append the positions sl0 + j of the set bits j of every lane's m to the queue qq
+    // (len entries, room for cap), in position order. flush() leaves fewer than 64
+    // entries; it runs when a step's positions might not fit, and between windows when
+    // they do not fit at all (position k of the step is the k-th in position order).
+    template <class Flush>
+    __device__ __forceinline__ void push(uint16_t *qq, uint32_t &len, uint32_t cap, uint32_t m, uint32_t sl0,
+                                         Flush flush) {
         if (!__ballot(m != 0)) return;
         const uint32_t c = __builtin_popcount(m);
         const uint32_t inc = wave_incl_scan(c);
         const uint32_t tot = __builtin_amdgcn_readlane(inc, 63);
-        if (S.qlen + tot > kQCap) drain(S);  // now qlen < 64
-        if (S.qlen + tot <= kQCap) {
-            uint32_t at = S.qlen + inc - c;
+        if (len + tot > cap) flush();  // now len < 64
+        if (len + tot <= cap) {
+            uint32_t at = len + inc - c;
             while (m) {
                 const uint32_t j = __builtin_ctz(m);
                 m &= m - 1;
-                q[at++] = (uint16_t)(sl0 + j);
+                qq[at++] = (uint16_t)(sl0 + j);
             }
-            S.qlen += tot;
+            len += tot;
             __builtin_amdgcn_wave_barrier();
             return;
         }
-        // more survivors in this step than the queue holds: queue them a window at a
-        // time (survivor k of the step is the k-th in position order), walking between
         for (uint32_t done = 0; done < tot;) {
-            const uint32_t room = kQCap - S.qlen;
+            const uint32_t room = cap - len;
             const uint32_t w = room < tot - done ? room : tot - done;
             uint32_t mm = m, k = inc - c;
             while (mm) {
                 const uint32_t j = __builtin_ctz(mm);
                 mm &= mm - 1;
-                if (k >= done && k < done + w) q[S.qlen + (k - done)] = (uint16_t)(sl0 + j);
+                if (k >= done && k < done + w) qq[len + (k - done)] = (uint16_t)(sl0 + j);
                 k++;
             }
             __builtin_amdgcn_wave_barrier();
-            S.qlen += w;
+            len += w;
             done += w;
-            if (done < tot) drain(S);
+            if (done < tot) flush();
         }
     }
 
-    // A lane's bytes of one step: kLaneBytes (16 or 32) consecutive text bytes, with the
-    // two-bit codes of each 16 when symbols are two-bit codes.
-    struct Chunk {
-        uint4 v[kLaneBytes / 16];
-    };
+    // Survivors of one step to the survivor queue. Walks wait until the queue might not
+    // hold another step (or the span ends).
+    __device__ __forceinline__ void take(SpanState &S, uint32_t m, uint32_t sl0) {
+        push(q, S.qlen, kQCap, m, sl0, [&] { drain(S); });
+    }
+
+    // Sampled prefilter: check `cnt` listed candidates from cq[first], one per lane. A
+    // candidate j stands for the starts j-1 and j; each start's 4-gram, read from the
+    // staged step, is tested against the two-probe filter, and the starts that pass join
+    // the survivor queue, in position order.
+    __device__ __forceinline__ void check_batch(SpanState &S, uint64_t step, uint32_t first, uint32_t cnt) {
+        const uint32_t lane = lane_id();
+        const bool on = lane < cnt;
+        const uint32_t j = on ? cq[first + lane] : 1u;  // odd: bytes j-1 .. j+3 lie in two words
+        const uint32_t *st = reinterpret_cast<const uint32_t *>(stg) + ((j - 1) >> 2);
+        const uint32_t w0 = st[0], w1 = st[1];
+        const uint32_t k0 = __builtin_amdgcn_alignbyte(w1, w0, (j - 1) & 3u);
+        const uint32_t k1 = __builtin_amdgcn_alignbyte(w1, w0, j & 3u);
+        uint32_t p0 = probe4s_first(W.img, k0), p1 = probe4s_first(W.img, k1);
+        if (p0 | p1) {  // few pass the first probe: the second only for them
+            p0 &= probe4s_second(W.img, k0);
+            p1 &= probe4s_second(W.img, k1);
+        }
+        const uint64_t s0 = step + j - 1;
+        p0 &= (uint32_t)(on && s0 < S.top);
+        p1 &= (uint32_t)(on && s0 + 1 < S.top);
+        const uint64_t b0 = __ballot(p0 != 0), b1 = __ballot(p1 != 0);
+        if (!(b0 | b1)) return;
+        const uint32_t tot = (uint32_t)(__builtin_popcountll(b0) + __builtin_popcountll(b1));
+        if (S.qlen + tot > kQCap) drain(S);  // now qlen < 64, and tot <= 128
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0u)) +
+                               __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
+        const uint32_t at = S.qlen + below;
+        const uint32_t sl = (uint32_t)(s0 - S.a);
+        if (p0) q[at] = (uint16_t)sl;
+        if (p1) q[at + p0] = (uint16_t)(sl + 1);
+        S.qlen += tot;
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // Sampled prefilter, one step: m holds this lane's candidates (bit j: start
+    // step + kLaneBytes * lane + j, j odd). The step's bytes go to the wave's staging
+    // area, the candidates to the list in position order, kCCap at a time, each window
+    // checked 64 at a time before the next is listed.
+    __device__ __forceinline__ void sample_step(SpanState &S, uint64_t step, const Chunk &cur, uint32_t nd,
+                                                uint32_t m) {
+        if (!__ballot(m != 0)) return;
+        const uint32_t lane = lane_id();
+#pragma unroll
+        for (uint32_t h = 0; h < kLaneBytes / 16; h++)
+            *reinterpret_cast<uint4 *>(stg + kLaneBytes * lane + 16 * h) = cur.v[h];
+        // the word after the lane's bytes: the next lane's first (the same value), and
+        // for the last lane the word after the step
+        *reinterpret_cast<uint32_t *>(stg + kLaneBytes * lane + kLaneBytes) = nd;
+        const uint32_t c = __builtin_popcount(m);
+        const uint32_t inc = wave_incl_scan(c);
+        const uint32_t tot = __builtin_amdgcn_readlane(inc, 63);
+        const uint32_t pos0 = kLaneBytes * lane;
+        for (uint32_t done = 0; done < tot; done += kCCap) {
+            const uint32_t w = tot - done < kCCap ? tot - done : kCCap;
+            uint32_t mm = m, k = inc - c - done;  // entry of this lane's first candidate in the window
+            __builtin_amdgcn_wave_barrier();
+            if (w == tot) {
+                while (mm) {
+                    const uint32_t j = __builtin_ctz(mm);
+                    mm &= mm - 1;
+                    cq[k++] = (uint16_t)(pos0 + j);
+                }
+            } else {  // entries outside the window wrap past w (unsigned) and are skipped
+                while (mm) {
+                    const uint32_t j = __builtin_ctz(mm);
+                    mm &= mm - 1;
+                    if (k < w) cq[k] = (uint16_t)(pos0 + j);
+                    k++;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t b = 0; b < w; b += 64) check_batch(S, step, b, w - b < 64 ? w - b : 64);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    // One step's prefilter mask: candidates (sampled prefilter) or survivors.
+    __device__ __forceinline__ void take_mask(SpanState &S, uint64_t step, const Chunk &cur, uint32_t nd, uint32_t m,
+                                              uint32_t sl0) {
+        if (FM == FM_K4 && !PACK2)
+            sample_step(S, step, cur, nd, m);
+        else
+            take(S, m, sl0);
+    }
+
     __device__ __forceinline__ Chunk chunk_buffer(__amdgpu_buffer_rsrc_t rs, uint32_t loff, uint32_t soff) const {
         Chunk c;
 #pragma unroll
@@ -666,9 +747,11 @@ struct Scanner {
             m |= prefilter16<PACK2, FM>(t, W.img, cur.v[h], nd, c0, c1) << (16 * h);
         }
         const uint32_t sl0 = (uint32_t)(step - S.a) + kLaneBytes * lane;  // span-local start of bit 0
-        if (step + kStep > top) {  // last step: keep starts below top
+        // last step: keep starts below top (a candidate j while j-1 is below it)
+        const uint64_t cut = FM == FM_K4 && !PACK2 ? top + 1 : top;
+        if (step + kStep > cut) {
             const uint64_t s0 = S.a + sl0;
-            if (s0 + kLaneBytes > top) m &= s0 >= top ? 0u : (uint32_t)((1ull << (uint32_t)(top - s0)) - 1ull);
+            if (s0 + kLaneBytes > cut) m &= s0 >= cut ? 0u : (uint32_t)((1ull << (uint32_t)(cut - s0)) - 1ull);
         }
         *sl0_out = sl0;
         return m;
@@ -692,11 +775,12 @@ struct Scanner {
     }
 
     // Count the span [S.a, hi).
-    __device__ void stream(SpanState &S, uint64_t hi) {
+    __device__ __forceinline__ void stream(SpanState &S, uint64_t hi) {
         const uint32_t lane = lane_id();
         uint64_t step = S.a;
         const uint64_t hiR = (hi + kStep - 1) & ~(uint64_t)(kStep - 1);  // end of the last step
         const uint64_t top = hi < lim ? hi : lim;
+        S.top = top;
         if (aligned && hiR + 16 <= n) {
             // Steady state: every load is an unconditional 16-byte load with no per-lane
             // test, kPrefetch steps ahead; addresses past the span are clamped to its last
@@ -717,7 +801,7 @@ struct Scanner {
                 next_lane_head(buf[0], buf[1 % kPrefetch], step == lastst, after, &nd, &nc);
                 uint32_t sl0;
                 const uint32_t m = mask_step(S, step, top, buf[0], nd, nc, &sl0);
-                take(S, m, sl0);
+                take_mask(S, step, buf[0], nd, m, sl0);
 #pragma unroll
                 for (uint32_t i = 0; i + 1 < kPrefetch; i++) buf[i] = buf[i + 1];
                 buf[kPrefetch - 1] = nxk;
@@ -734,7 +818,7 @@ struct Scanner {
                 next_lane_head(cur, nx1, false, make_uint4(0u, 0u, 0u, 0u), &nd, &nc);
                 uint32_t sl0;
                 const uint32_t m = mask_step(S, step, top, cur, nd, nc, &sl0);
-                take(S, m, sl0);
+                take_mask(S, step, cur, nd, m, sl0);
                 cur = nx1;
                 nx1 = nx2;
             }
@@ -761,13 +845,42 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     const uint64_t span_len = 1ull << span_log2;
     const uint32_t n_spans = (uint32_t)((n + span_len - 1) >> span_log2);
     {
-        // filter words to offset 0, root bitmap and rank table to their fixed places
-        const uint32_t fw = t.root_word, rw = t.rank_word - t.root_word, kw = t.short_word - t.rank_word,
-                       sw = t.lds_words - t.short_word;
-        for (uint32_t i = threadIdx.x; i < fw; i += kThreads) img[i] = t.lds_image[i];
-        for (uint32_t i = threadIdx.x; i < rw; i += kThreads) img[kLdsRoot + i] = t.lds_image[t.root_word + i];
-        for (uint32_t i = threadIdx.x; i < kw; i += kThreads) img[kLdsRank + i] = t.lds_image[t.rank_word + i];
-        for (uint32_t i = threadIdx.x; i < sw; i += kThreads) img[kLdsShort + i] = t.lds_image[t.short_word + i];
+        // filter words to offset 0 (16 bytes a load), root bitmap, rank table and short
+        // bitmap (one run in the image) to their fixed places. A thread issues all its
+        // loads of a round before its first store: one memory round trip per round,
+        // not one per word.
+        const uint32_t f4 = t.root_word / 4, rw = t.rank_word - t.root_word, kw = t.short_word - t.rank_word,
+                       small = t.lds_words - t.root_word;
+        const uint4 *__restrict__ fsrc = reinterpret_cast<const uint4 *>(t.lds_image);
+        const uint32_t *__restrict__ ssrc = t.lds_image + t.root_word;
+        constexpr uint32_t kF = 8, kS = 6;
+        for (uint32_t base = 0; base < f4 || base < small; base += kF * kThreads) {
+            uint4 fv[kF];
+            uint32_t sv[kS];
+#pragma unroll
+            for (uint32_t u = 0; u < kF; u++) {
+                const uint32_t i = base + u * kThreads + threadIdx.x;
+                fv[u] = i < f4 ? fsrc[i] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kS; u++) {
+                const uint32_t i = base + u * kThreads + threadIdx.x;
+                sv[u] = i < small ? ssrc[i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kF; u++) {
+                const uint32_t i = base + u * kThreads + threadIdx.x;
+                if (i < f4) reinterpret_cast<uint4 *>(img)[i] = fv[u];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kS; u++) {
+                const uint32_t i = base + u * kThreads + threadIdx.x;
+                if (i < small) img[i < rw ? kLdsRoot + i : i < rw + kw ? kLdsRank + (i - rw) : kLdsShort + (i - rw - kw)] = sv[u];
+            }
+            // words kS * kThreads and up of the small run (none at the shapes allowed)
+            for (uint32_t i = base + kS * kThreads + threadIdx.x; i < small && i < base + kF * kThreads; i += kThreads)
+                img[i < rw ? kLdsRoot + i : i < rw + kw ? kLdsRank + (i - rw) : kLdsShort + (i - rw - kw)] = ssrc[i];
+        }
     }
     __syncthreads();  // the only barrier: waves run independently from here
 
@@ -775,8 +888,10 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     // load offsets) then stays in scalar registers
     const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint16_t *wq = reinterpret_cast<uint16_t *>(img + kLdsQueues) + wave * kQCap;
+    uint16_t *wc = reinterpret_cast<uint16_t *>(img + kLdsCands) + wave * kCCap;
+    uint8_t *ws = reinterpret_cast<uint8_t *>(img + kLdsStage) + wave * kStageBytes;
     Scanner<LAYOUT, PACK2, SEG, FM> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
-                                   offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0};
+                                   offsets, n_packets, so, wq, wc, ws, (((uintptr_t)text) & 15) == 0};
     const uint32_t waves = gridDim.x * kWaves;
     for (uint32_t span = blockIdx.x * kWaves + wave; span < n_spans; span += waves) {
         SpanState S{(uint64_t)span << span_log2, span, 0, 0, kNone, 0};

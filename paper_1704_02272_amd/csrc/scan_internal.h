@@ -51,22 +51,25 @@ constexpr uint32_t kDirectMaxSpans = 16384;  // placement without look-back up t
 constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement wave issues together
 constexpr uint32_t kPlaceThreads = 256;
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
+constexpr uint32_t kCCap = 256;      // sampled prefilter: candidates a wave checks per window
 constexpr uint32_t kWaveLds = kQCap * 2;  // bytes of LDS per wave (survivor queue)
 static_assert(kWaveLds % 16 == 0, "wave regions stay 16-byte aligned");
-static_assert(kQCap >= 128, "a queue holds at least two walk batches");
+static_assert(kQCap >= 192, "a queue below 64 entries takes a refined batch (up to 128)");
+static_assert(kCCap >= 64 && kCCap % 64 == 0, "a candidate window is whole batches");
 
-// Fixed LDS layout of the scan kernel (32-bit words): a 112 KiB prefilter region at
-// offset 0, then the root bitmap and its rank table, the short-pattern bitmap and the
-// per-wave queues. The prefilter region holds one of two layouts (a probe's masked hash
-// plus its part's compile-time offset is its byte address):
+// Fixed LDS layout of the scan kernel (32-bit words): the prefilter region at offset 0,
+// then the root bitmap and its rank table, the short-pattern bitmap, the per-wave
+// survivor queues and the per-wave candidate lists. The prefilter region holds one of two
+// layouts (a probe's masked hash plus its part's compile-time offset is its byte address):
 //   general   [second-probe part: 2^18 bits][first-probe part: 2^19 bits]
 //             two-probe Bloom filter over k-gram keys, every start probed
-//   sampled   [second-probe part: 2^17 bits][first-probe part: 2^18 bits][3-gram part: 2^19 bits]
+//   sampled   [second-probe part: 2^15 bits][first-probe part: 2^16 bits][3-gram part: 2^19 bits]
+//             [text staging: one step of bytes per wave]
 //             patterns of four or more bytes and k = 4: only every second start is
 //             probed, with the 3-gram there against the 3-grams at offsets 0 and 1 of
 //             every pattern; the two starts it stands for are then checked against the
-//             two-probe Bloom filter over 4-grams.
-// Every part starts below 64 KiB, so its offset folds into the LDS instruction.
+//             two-probe Bloom filter over 4-grams, read from the staged step.
+// Every filter part starts below 64 KiB, so its offset folds into the LDS instruction.
 constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;    // general first-probe part: 2^19 bits
 constexpr uint32_t kFilter2Log2 = PFAC_FILTER2_LOG2;     // general second-probe part: 2^18 bits
 constexpr uint32_t kFilterWordsMax = 1u << (kMaxFilterLog2 - 5);
@@ -75,12 +78,19 @@ constexpr uint32_t kLdsF1 = kFilter2Words;                // word offset of the 
 constexpr uint32_t kAmask1 = (kFilterWordsMax - 1u) << 2; // byte-offset masks of the parts
 constexpr uint32_t kAmask2 = (kFilter2Words - 1u) << 2;
 constexpr uint32_t kS3Words = 1u << 14;                   // sampled: 3-gram part (64 KiB)
-constexpr uint32_t kS2Words = 1u << 12;                   // sampled: second-probe part (16 KiB)
-constexpr uint32_t kS1Words = 1u << 13;                   // sampled: first-probe part (32 KiB)
+constexpr uint32_t kS2Words = 1u << 10;                   // sampled: second-probe part (4 KiB)
+constexpr uint32_t kS1Words = 1u << 11;                   // sampled: first-probe part (8 KiB)
 constexpr uint32_t kLdsS2 = 0, kLdsS1 = kS2Words, kLdsS3 = kS2Words + kS1Words;
 static_assert(kLdsS3 * 4 < 65536, "the 3-gram part's offset fits the LDS instruction");
-constexpr uint32_t kFilterRegionWords = kS3Words + kS2Words + kS1Words;
-static_assert(kFilterRegionWords >= kFilter2Words + kFilterWordsMax, "both layouts fit the region");
+constexpr uint32_t kSampledWords = kLdsS3 + kS3Words;     // the sampled filter's words
+constexpr uint32_t kStageBytes = kStep + 16;              // a wave's step and the word after it
+static_assert(kStageBytes % 16 == 0, "staged steps stay 16-byte aligned");
+constexpr uint32_t kLdsStage = kSampledWords;
+constexpr uint32_t kSampledRegionWords = kLdsStage + kWaves * kStageBytes / 4;
+constexpr uint32_t kGeneralRegionWords = kFilter2Words + kFilterWordsMax;
+constexpr uint32_t kFilterRegionWords =
+    kSampledRegionWords > kGeneralRegionWords ? kSampledRegionWords : kGeneralRegionWords;
+static_assert(kSampledWords % 4 == 0 && kGeneralRegionWords % 4 == 0, "filters copy in 16-byte units");
 constexpr uint32_t kFilterMul3 = 0x9E3779u;  // 24-bit multiplier of the 3-gram hash
 constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
@@ -88,7 +98,8 @@ constexpr uint32_t kLdsRoot = kFilterRegionWords;
 constexpr uint32_t kLdsRank = kLdsRoot + kRootWordsMax;
 constexpr uint32_t kLdsShort = kLdsRank + kRankWordsMax;
 constexpr uint32_t kLdsQueues = kLdsShort + kRootWordsMax;
-constexpr uint32_t kLdsWords = kLdsQueues + kWaves * kWaveLds / 4;
+constexpr uint32_t kLdsCands = kLdsQueues + kWaves * kWaveLds / 4;
+constexpr uint32_t kLdsWords = kLdsCands + kWaves * kCCap / 2;
 
 // Per-span results of the count kernel (device memory, owned by a workspace).
 //   cnt[s]   matches in span s          nh[s]   records stored for span s
