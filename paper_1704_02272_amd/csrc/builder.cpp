@@ -134,7 +134,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     // every depth-D node is a D-prefix of some pattern (D <= shortest length)
     if (run != a->depth_start[D + 1] - a->depth_start[D]) throw std::bad_alloc();
     if (t.sampled) {
-        for (uint32_t key : fkeys) filter_insert(img, key, kLdsS1, kS1Words, kLdsS2, kS2Words);
+        for (uint32_t key : fkeys) filter4s_insert(img, key, kLdsS1, kS1Words, kLdsS2, kS2Words);
         for (uint32_t j = 0; j < a->n_pats; j++) {
             const uint8_t *p = P[j];  // every pattern has four or more bytes here
             filter3_insert(img, (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16), kFilterMul3, kLdsS3, kS3Words);

@@ -56,11 +56,13 @@ constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShl1 = 0x1
 
 // Inclusive prefix sum over the wave: shifts within each 16-lane row, then the row
 // totals carried into the rows above.
+// The row shifts read 0 where the source lane is outside the row (bound control), so
+// they need no zeroed register and fold into the adds.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr1, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr2, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr4, 0xf, 0xf, false);
-    v += __builtin_amdgcn_update_dpp(0u, v, kDppRowShr8, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowShr1, 0xf, 0xf, true);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowShr2, 0xf, 0xf, true);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowShr4, 0xf, 0xf, true);
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowShr8, 0xf, 0xf, true);
     v += __builtin_amdgcn_update_dpp(0u, v, kDppRowBcast15, 0xa, 0xf, false);
     v += __builtin_amdgcn_update_dpp(0u, v, kDppRowBcast31, 0xc, 0xf, false);
     return v;
@@ -71,10 +73,29 @@ __device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
     return __builtin_amdgcn_update_dpp(0u, v, kDppWaveShl1, 0xf, 0xf, false);
 }
 
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+// 64-bit forms: the same lane moves on both halves, then a 64-bit add.
+__device__ __forceinline__ uint64_t dpp_pair(uint64_t v, uint32_t lo_moved, uint32_t hi_moved) {
+    return v + (((uint64_t)hi_moved << 32) | lo_moved);
+}
+#define PFAC_DPP64(v, ctrl, rm)                                                                          \
+    dpp_pair(v, __builtin_amdgcn_update_dpp(0u, (uint32_t)(v), ctrl, rm, 0xf, false),                  \
+             __builtin_amdgcn_update_dpp(0u, (uint32_t)((v) >> 32), ctrl, rm, 0xf, false))
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+    v = PFAC_DPP64(v, kDppRowShr1, 0xf);
+    v = PFAC_DPP64(v, kDppRowShr2, 0xf);
+    v = PFAC_DPP64(v, kDppRowShr4, 0xf);
+    v = PFAC_DPP64(v, kDppRowShr8, 0xf);
+    v = PFAC_DPP64(v, kDppRowBcast15, 0xa);
+    v = PFAC_DPP64(v, kDppRowBcast31, 0xc);
     return v;
+}
+#undef PFAC_DPP64
+
+// Sum over the wave, in every lane.
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+    const uint64_t s = wave_incl_scan64(v);
+    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(s >> 32), 63) << 32) |
+           __builtin_amdgcn_readlane((uint32_t)s, 63);
 }
 
 // ------------------------------------------------------------------------ the walk
@@ -362,15 +383,14 @@ __device__ __forceinline__ uint32_t probe3(const uint32_t *img, uint32_t x) {
     return __builtin_amdgcn_ubfe(w, x, 1);
 }
 __device__ __forceinline__ uint32_t probe4s_first(const uint32_t *img, uint32_t key) {
-    const uint32_t o1 = (__umulhi(key, kFilterMul) & ((kS1Words - 1u) << 2)) + kLdsS1 * 4;
+    const uint32_t o1 = ((s1_hash(key) >> 16) & ((kS1Words - 1u) << 2)) + kLdsS1 * 4;
     const uint32_t w1 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o1);
     return __builtin_amdgcn_ubfe(w1, key, 1);
 }
 __device__ __forceinline__ uint32_t probe4s_second(const uint32_t *img, uint32_t key) {
-    const uint32_t h2 = __umulhi(key, kFilterMul2);
-    const uint32_t o2 = (h2 & ((kS2Words - 1u) << 2)) + kLdsS2 * 4;
+    const uint32_t o2 = ((s2_hash(key) >> 16) & ((kS2Words - 1u) << 2)) + kLdsS2 * 4;
     const uint32_t w2 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o2);
-    return (w2 >> (h2 >> 27)) & 1u;
+    return __builtin_amdgcn_ubfe(w2, key >> 24, 1);
 }
 
 // Four bytes starting at byte j (0..15) of the 20 bytes v, d4 (little-endian words).
@@ -936,9 +956,12 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
     uint32_t next_blk = blockIdx.x;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const Trie<LAYOUT> T{t};
-    if (threadIdx.x == 0) sh[1] = __hip_atomic_load(&ts.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const uint32_t epoch = sh[1];
+    uint32_t epoch = 0;  // look-back words' epoch (not used by direct placement)
+    if (!direct) {
+        if (threadIdx.x == 0) sh[1] = __hip_atomic_load(&ts.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        epoch = sh[1];
+    }
     const uint64_t tagE = (uint64_t)epoch << 44;
     auto end_of = [&](uint64_t s) -> uint64_t {
         if (!SEG) return n;
@@ -959,19 +982,30 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
         if (blk >= n_blocks) break;
         // wave 0, lane i: span i of the block; its count, record count, overflow and first
         // records, all loaded at once (records past the stored ones are read and ignored)
+        // Loads go out unconditionally from clamped indices (no branch around any of them),
+        // so every one of a lane's loads is in flight at once; the selects come after.
         const uint32_t my_sp = blk * kBlockSpans + lane;
         const bool my_in = wave == 0 && my_sp < n_spans;
-        const uint64_t my_c = my_in ? so.cnt[my_sp] : 0;
-        const uint32_t my_nh = my_in ? so.nh[my_sp] : 0, my_ovf = my_in ? so.ovf[my_sp] : kNone;
+        const uint32_t sp_c = my_in ? my_sp : 0u;
+        const uint64_t c_ld = so.cnt[sp_c];
+        const uint32_t nh_ld = so.nh[sp_c], ovf_ld = so.ovf[sp_c];
         uint64_t my_rec[kFastRecs];
 #pragma unroll
-        for (uint32_t k = 0; k < kFastRecs; k++) my_rec[k] = my_in ? so.rec[((size_t)my_sp << so.rec_log2) + k] : 0;
+        for (uint32_t k = 0; k < kFastRecs; k++) my_rec[k] = so.rec[((size_t)sp_c << so.rec_log2) + k];
         uint64_t before = 0;  // matches in spans before this block (direct mode)
         if (direct) {
             uint64_t part = 0;
             const uint32_t lim_s = blk * kBlockSpans;
-#pragma unroll 8
-            for (uint32_t s = threadIdx.x; s < lim_s; s += kPlaceThreads) part += so.cnt[s];
+            for (uint32_t s0 = 0; s0 < lim_s; s0 += 16 * kPlaceThreads) {
+                uint64_t v[16];
+#pragma unroll
+                for (uint32_t u = 0; u < 16; u++) {
+                    const uint32_t s = s0 + u * kPlaceThreads + threadIdx.x;
+                    v[u] = so.cnt[s < lim_s ? s : 0u];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < 16; u++) part += s0 + u * kPlaceThreads + threadIdx.x < lim_s ? v[u] : 0u;
+            }
             part = wave_sum64(part);
             if (lane == 0) pre[wave] = part;
             __syncthreads();
@@ -979,19 +1013,17 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             for (uint32_t w = 0; w < kPlaceWaves; w++) before += pre[w];
             __syncthreads();  // pre[] is rewritten by the next block
         }
+        const uint64_t my_c = my_in ? c_ld : 0u;
+        const uint32_t my_nh = my_in ? nh_ld : 0u, my_ovf = my_in ? ovf_ld : kNone;
         if (wave == 0) {
             // the block's span counts, their prefix, and the block's place by look-back
             const uint64_t c = my_c;
             const uint32_t nh = my_nh, ovf = my_ovf;
             span_nh[lane] = nh;
             span_cls[lane] = c == 0 ? 0u : (ovf == kNone && nh <= kFastRecs) ? 1u : 2u;
-            uint64_t inc = c;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint64_t u = __shfl_up(inc, d, 64);
-                if (lane >= (uint32_t)d) inc += u;
-            }
-            const uint64_t total = __shfl(inc, 63, 64);
+            const uint64_t inc = wave_incl_scan64(c);
+            const uint64_t total = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(inc >> 32), 63) << 32) |
+                                   __builtin_amdgcn_readlane((uint32_t)inc, 63);
             if (direct && lane == 0 && blk == n_blocks - 1) *d_count = before + total;
             if (!direct && lane == 0) {
                 const uint64_t v = total > kValueMask ? kValueMask : total;
