@@ -111,7 +111,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     // four-byte keys and no shorter pattern: the sampled layout
     t.sampled = (!t.pack2 && t.filter_k == 4 && !any_short) ? 1u : 0u;
     // the image holds the filter words the kernel copies to LDS offset 0
-    const uint32_t filter_words = !flog2 ? 0 : t.sampled ? kSampledWords : kGeneralRegionWords;
+    const uint32_t filter_words = !flog2 ? 0 : t.sampled ? kSampledWords : kGeneralWords;
     t.root_word = filter_words;
     t.rank_word = filter_words + root_words;
     t.short_word = t.rank_word + rank_words;

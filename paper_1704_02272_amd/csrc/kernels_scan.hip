@@ -246,7 +246,7 @@ struct Trie {
 // Walk of a survivor in the count kernel: the first D symbols through the LDS root
 // image, the rest through the trie in HBM. The first eight text bytes come from one
 // round of independent loads.
-template <int LAYOUT, bool PACK2>
+template <int LAYOUT, bool PACK2, bool SAMPLED>
 struct RootWalk {
     const DevTable &t;
     const uint8_t *__restrict__ text;
@@ -266,9 +266,9 @@ struct RootWalk {
             key = (key << (PACK2 ? 2 : 8)) | c;
         }
         const uint32_t wi = key >> 5, b = key & 31;
-        const uint32_t word = img[kLdsRoot + wi];
+        const uint32_t word = img[Lds<SAMPLED>::root + wi];
         if (!((word >> b) & 1u)) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + kLdsRank);
+        const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + Lds<SAMPLED>::rank);
         uint32_t q = t.root_base + rank[wi] + __builtin_popcount(word & ((1u << b) - 1u));
         // continue with the bytes already loaded, then one load per level
         const Trie<LAYOUT> T{t};
@@ -433,7 +433,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         } else if (FM == FM_GEN) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
             const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : (1u << (8 * t.filter_k)) - 1u;
-            const uint32_t *shrt = img + kLdsShort;
+            const uint32_t *shrt = img + Lds<false>::shrt;
             const bool two = t.root_depth == 2, sh = t.has_short;
             uint32_t ms = 0;
 #pragma unroll
@@ -454,7 +454,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
             mask |= ms;
         } else {
             // root image as the filter: D-byte key, first byte most significant
-            const uint32_t *root = img + kLdsRoot;
+            const uint32_t *root = img + Lds<false>::root;
             const bool two = t.root_depth == 2;
 #pragma unroll
             for (int j = 15; j >= 0; j--) {
@@ -469,7 +469,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         const uint32_t rs = 32 - 2 * K;
         if (FM != FM_ROOT) {
             // k-gram filter, plus the short bitmap (D-grams) for patterns shorter than k
-            const uint32_t *shrt = img + kLdsShort;
+            const uint32_t *shrt = img + Lds<false>::shrt;
             const uint32_t rsd = 32 - 2 * t.root_depth;
             const bool sh = t.has_short;
             uint32_t ms = 0;
@@ -488,7 +488,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
             }
             mask |= ms;
         } else {
-            const uint32_t *root = img + kLdsRoot;
+            const uint32_t *root = img + Lds<false>::root;
 #pragma unroll
             for (int j = 15; j >= 0; j--) {
                 const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
@@ -513,13 +513,15 @@ struct SpanState {
 template <int LAYOUT, bool PACK2, bool SEG, int FM>
 struct Scanner {
     const DevTable &t;
-    RootWalk<LAYOUT, PACK2> W;
+    static constexpr bool kSampled = FM == FM_K4 && !PACK2;
+    static constexpr uint32_t kQ = Lds<kSampled>::qcap;  // survivor queue entries
+    RootWalk<LAYOUT, PACK2, kSampled> W;
     const uint8_t *__restrict__ text;
     uint64_t n, lim;  // starts >= lim cannot match (too little text left)
     const uint64_t *__restrict__ offsets;
     uint32_t n_packets;
     SpanOut so;
-    uint16_t *q;  // survivor queue (span-local starts), kQCap entries
+    uint16_t *q;  // survivor queue (span-local starts), kQ entries
     uint16_t *cq; // sampled prefilter: candidate list (step-local odd starts), kCCap entries
     uint8_t *stg; // sampled prefilter: this wave's staged step (kStageBytes)
     bool aligned;
@@ -650,7 +652,7 @@ struct Scanner {
     // Survivors of one step to the survivor queue. Walks wait until the queue might not
     // hold another step (or the span ends).
     __device__ __forceinline__ void take(SpanState &S, uint32_t m, uint32_t sl0) {
-        push(q, S.qlen, kQCap, m, sl0, [&] { drain(S); });
+        push(q, S.qlen, kQ, m, sl0, [&] { drain(S); });
     }
 
     // Sampled prefilter: check `cnt` listed candidates from cq[first], one per lane. A
@@ -676,7 +678,7 @@ struct Scanner {
         const uint64_t b0 = __ballot(p0 != 0), b1 = __ballot(p1 != 0);
         if (!(b0 | b1)) return;
         const uint32_t tot = (uint32_t)(__builtin_popcountll(b0) + __builtin_popcountll(b1));
-        if (S.qlen + tot > kQCap) drain(S);  // now qlen < 64, and tot <= 128
+        if (S.qlen + tot > kQ) drain(S);  // now qlen < 64, and tot <= 128
         const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0u)) +
                                __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
         const uint32_t at = S.qlen + below;
@@ -732,7 +734,7 @@ struct Scanner {
     // One step's prefilter mask: candidates (sampled prefilter) or survivors.
     __device__ __forceinline__ void take_mask(SpanState &S, uint64_t step, const Chunk &cur, uint32_t nd, uint32_t m,
                                               uint32_t sl0) {
-        if (FM == FM_K4 && !PACK2)
+        if (kSampled)
             sample_step(S, step, cur, nd, m);
         else
             take(S, m, sl0);
@@ -857,7 +859,8 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
                                                       const uint64_t *__restrict__ offsets, uint32_t n_packets,
                                                       SpanOut so, const uint64_t *__restrict__ sizes,
                                                       uint32_t span_log2) {
-    __shared__ __align__(16) uint32_t img[kLdsWords];
+    using L = Lds<FM == FM_K4 && !PACK2>;
+    __shared__ __align__(16) uint32_t img[L::words];
     if (sizes) {  // sizes of this batch, bounded by those the launch was set up for
         n = sizes[0] < n ? sizes[0] : n;
         n_packets = sizes[1] < n_packets ? (uint32_t)sizes[1] : n_packets;
@@ -895,11 +898,11 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
 #pragma unroll
             for (uint32_t u = 0; u < kS; u++) {
                 const uint32_t i = base + u * kThreads + threadIdx.x;
-                if (i < small) img[i < rw ? kLdsRoot + i : i < rw + kw ? kLdsRank + (i - rw) : kLdsShort + (i - rw - kw)] = sv[u];
+                if (i < small) img[i < rw ? L::root + i : i < rw + kw ? L::rank + (i - rw) : L::shrt + (i - rw - kw)] = sv[u];
             }
             // words kS * kThreads and up of the small run (none at the shapes allowed)
             for (uint32_t i = base + kS * kThreads + threadIdx.x; i < small && i < base + kF * kThreads; i += kThreads)
-                img[i < rw ? kLdsRoot + i : i < rw + kw ? kLdsRank + (i - rw) : kLdsShort + (i - rw - kw)] = ssrc[i];
+                img[i < rw ? L::root + i : i < rw + kw ? L::rank + (i - rw) : L::shrt + (i - rw - kw)] = ssrc[i];
         }
     }
     __syncthreads();  // the only barrier: waves run independently from here
@@ -907,9 +910,9 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     // the wave index through a scalar register: everything derived from it (span, step,
     // load offsets) then stays in scalar registers
     const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    uint16_t *wq = reinterpret_cast<uint16_t *>(img + kLdsQueues) + wave * kQCap;
-    uint16_t *wc = reinterpret_cast<uint16_t *>(img + kLdsCands) + wave * kCCap;
-    uint8_t *ws = reinterpret_cast<uint8_t *>(img + kLdsStage) + wave * kStageBytes;
+    uint16_t *wq = reinterpret_cast<uint16_t *>(img + L::queues) + wave * L::qcap;
+    uint16_t *wc = reinterpret_cast<uint16_t *>(img + L::cands) + wave * kCCap;      // sampled only
+    uint8_t *ws = reinterpret_cast<uint8_t *>(img + L::stage) + wave * kStageBytes;  // sampled only
     Scanner<LAYOUT, PACK2, SEG, FM> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
                                    offsets, n_packets, so, wq, wc, ws, (((uintptr_t)text) & 15) == 0};
     const uint32_t waves = gridDim.x * kWaves;

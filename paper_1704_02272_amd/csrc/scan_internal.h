@@ -42,7 +42,6 @@ constexpr uint32_t kMinSpanLog2 = kLaneBytes == 16 ? 10 : 11;  // a span holds a
 constexpr uint32_t kMaxSpanLog2 = 16; // span-local starts are 16-bit
 constexpr uint32_t kPrefetch = PFAC_PREFETCH;  // text loads in flight per lane, in wave steps (>= 2)
 static_assert(PFAC_PREFETCH >= 2, "the next step's first word comes from the prefetch");
-constexpr uint32_t kQCap = PFAC_QCAP;  // survivor queue; walked when a step might not fit, and at the span end
 constexpr uint32_t kHCapMinLog2 = 8; // match records kept per span: span / 64, at least 256
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
 constexpr uint32_t kRecMulti = 0x8000;  // record flag: several terminals (see SpanOut)
@@ -51,25 +50,25 @@ constexpr uint32_t kDirectMaxSpans = 16384;  // placement without look-back up t
 constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement wave issues together
 constexpr uint32_t kPlaceThreads = 256;
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
-constexpr uint32_t kCCap = 256;      // sampled prefilter: candidates a wave checks per window
-constexpr uint32_t kWaveLds = kQCap * 2;  // bytes of LDS per wave (survivor queue)
-static_assert(kWaveLds % 16 == 0, "wave regions stay 16-byte aligned");
-static_assert(kQCap >= 192, "a queue below 64 entries takes a refined batch (up to 128)");
-static_assert(kCCap >= 64 && kCCap % 64 == 0, "a candidate window is whole batches");
+constexpr uint32_t kStepLog2 = kLaneBytes == 16 ? 10 : 11;
+static_assert((1u << kStepLog2) == kStep, "step length is a power of two");
 
-// Fixed LDS layout of the scan kernel (32-bit words): the prefilter region at offset 0,
-// then the root bitmap and its rank table, the short-pattern bitmap, the per-wave
-// survivor queues and the per-wave candidate lists. The prefilter region holds one of two
-// layouts (a probe's masked hash plus its part's compile-time offset is its byte address):
-//   general   [second-probe part: 2^18 bits][first-probe part: 2^19 bits]
-//             two-probe Bloom filter over k-gram keys, every start probed
-//   sampled   [second-probe part: 2^15 bits][first-probe part: 2^16 bits][3-gram part: 2^19 bits]
-//             [text staging: one step of bytes per wave]
+// LDS of the scan kernel (32-bit words), one of two layouts per kernel instance (a
+// probe's masked hash plus its part's compile-time offset is its byte address; every
+// filter part starts below 64 KiB, so that offset folds into the LDS instruction):
+//   general   [second-probe part: 2^18 bits][first-probe part: 2^19 bits][short bitmap]
+//             [root bitmap][rank table][survivor queues, 512 entries a wave]
+//             two-probe Bloom filter over k-gram keys, every start probed; the short
+//             bitmap holds the D-grams of patterns shorter than k
+//   sampled   [second-probe part: 2^16 bits][first-probe part: 2^17 bits][3-gram part: 2^19 bits]
+//             [text staging: one step a wave][root bitmap][rank table]
+//             [survivor queues, 512 entries a wave][candidate lists, kCCap entries a wave]
 //             patterns of four or more bytes and k = 4: only every second start is
 //             probed, with the 3-gram there against the 3-grams at offsets 0 and 1 of
 //             every pattern; the two starts it stands for are then checked against the
 //             two-probe Bloom filter over 4-grams, read from the staged step.
-// Every filter part starts below 64 KiB, so its offset folds into the LDS instruction.
+// The builder's image holds the filter words (copied to offset 0), then the root bitmap,
+// the rank table and the short bitmap (copied to their places).
 constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;    // general first-probe part: 2^19 bits
 constexpr uint32_t kFilter2Log2 = PFAC_FILTER2_LOG2;     // general second-probe part: 2^18 bits
 constexpr uint32_t kFilterWordsMax = 1u << (kMaxFilterLog2 - 5);
@@ -77,29 +76,48 @@ constexpr uint32_t kFilter2Words = 1u << (kFilter2Log2 - 5);
 constexpr uint32_t kLdsF1 = kFilter2Words;                // word offset of the first-probe part
 constexpr uint32_t kAmask1 = (kFilterWordsMax - 1u) << 2; // byte-offset masks of the parts
 constexpr uint32_t kAmask2 = (kFilter2Words - 1u) << 2;
+constexpr uint32_t kGeneralWords = kFilter2Words + kFilterWordsMax;  // general filter words
 constexpr uint32_t kS3Words = 1u << 14;                   // sampled: 3-gram part (64 KiB)
-constexpr uint32_t kS2Words = 1u << 10;                   // sampled: second-probe part (4 KiB)
-constexpr uint32_t kS1Words = 1u << 11;                   // sampled: first-probe part (8 KiB)
+constexpr uint32_t kS2Words = 1u << 11;                   // sampled: second-probe part (8 KiB)
+constexpr uint32_t kS1Words = 1u << 12;                   // sampled: first-probe part (16 KiB)
 constexpr uint32_t kLdsS2 = 0, kLdsS1 = kS2Words, kLdsS3 = kS2Words + kS1Words;
 static_assert(kLdsS3 * 4 < 65536, "the 3-gram part's offset fits the LDS instruction");
-constexpr uint32_t kSampledWords = kLdsS3 + kS3Words;     // the sampled filter's words
-constexpr uint32_t kStageBytes = kStep + 16;              // a wave's step and the word after it
-static_assert(kStageBytes % 16 == 0, "staged steps stay 16-byte aligned");
-constexpr uint32_t kLdsStage = kSampledWords;
-constexpr uint32_t kSampledRegionWords = kLdsStage + kWaves * kStageBytes / 4;
-constexpr uint32_t kGeneralRegionWords = kFilter2Words + kFilterWordsMax;
-constexpr uint32_t kFilterRegionWords =
-    kSampledRegionWords > kGeneralRegionWords ? kSampledRegionWords : kGeneralRegionWords;
-static_assert(kSampledWords % 4 == 0 && kGeneralRegionWords % 4 == 0, "filters copy in 16-byte units");
+constexpr uint32_t kSampledWords = kLdsS3 + kS3Words;     // sampled filter words
+static_assert(kSampledWords % 4 == 0 && kGeneralWords % 4 == 0, "filters copy in 16-byte units");
 constexpr uint32_t kFilterMul3 = 0x9E3779u;  // 24-bit multiplier of the 3-gram hash
 constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
-constexpr uint32_t kLdsRoot = kFilterRegionWords;
-constexpr uint32_t kLdsRank = kLdsRoot + kRootWordsMax;
-constexpr uint32_t kLdsShort = kLdsRank + kRankWordsMax;
-constexpr uint32_t kLdsQueues = kLdsShort + kRootWordsMax;
-constexpr uint32_t kLdsCands = kLdsQueues + kWaves * kWaveLds / 4;
-constexpr uint32_t kLdsWords = kLdsCands + kWaves * kCCap / 2;
+constexpr uint32_t kStageBytes = kStep + 16;              // sampled: a step and the word after it
+static_assert(kStageBytes % 16 == 0, "staged steps stay 16-byte aligned");
+constexpr uint32_t kCCap = 128;                           // sampled: candidates listed at a time
+static_assert(kCCap >= 64 && kCCap % 64 == 0, "a candidate window is whole batches");
+
+template <bool SAMPLED>
+struct Lds;
+template <>
+struct Lds<false> {
+    static constexpr uint32_t shrt = kGeneralWords;
+    static constexpr uint32_t root = shrt + kRootWordsMax;
+    static constexpr uint32_t rank = root + kRootWordsMax;
+    static constexpr uint32_t qcap = PFAC_QCAP;
+    static constexpr uint32_t queues = rank + kRankWordsMax;
+    static constexpr uint32_t stage = 0, cands = 0;  // none
+    static constexpr uint32_t words = queues + kWaves * qcap / 2;
+};
+template <>
+struct Lds<true> {
+    static constexpr uint32_t stage = kSampledWords;
+    static constexpr uint32_t root = stage + kWaves * kStageBytes / 4;
+    static constexpr uint32_t rank = root + kRootWordsMax;
+    static constexpr uint32_t shrt = 0;  // none: no pattern is shorter than k
+    static constexpr uint32_t qcap = PFAC_QCAP;
+    static constexpr uint32_t queues = rank + kRankWordsMax;
+    static constexpr uint32_t cands = queues + kWaves * qcap / 2;
+    static constexpr uint32_t words = cands + kWaves * kCCap / 2;
+};
+static_assert(Lds<false>::qcap >= 128 && Lds<false>::qcap % 8 == 0, "a queue holds two walk batches");
+static_assert(Lds<true>::qcap >= 192, "a queue below 64 entries takes a checked batch (up to 128)");
+static_assert(Lds<false>::words * 4 <= 160 * 1024 && Lds<true>::words * 4 <= 160 * 1024, "LDS of one CU");
 
 // Per-span results of the count kernel (device memory, owned by a workspace).
 //   cnt[s]   matches in span s          nh[s]   records stored for span s
