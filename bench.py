@@ -47,11 +47,17 @@ KERNEL_SOURCES = ["paper_1704_02272_amd/csrc/kernels_scan.hip",
 
 
 def source_digest() -> str:
+    """Digest of the kernel sources' code: comments (from // to the end of a line) and
+    blank lines are left out, so a comment edit does not count as a kernel change."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         p = os.path.join(ROOT, rel)
-        if os.path.exists(p):
-            h.update(open(p, "rb").read())
+        if not os.path.exists(p):
+            continue
+        for line in open(p, encoding="utf-8"):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

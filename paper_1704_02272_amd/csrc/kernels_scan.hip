@@ -7,14 +7,17 @@
 //
 // Count kernel (scan_count), one persistent wave per span at a time, no wave ever
 // waiting on another:
-//  * Spans. The text is cut into spans of 2^span_log2 bytes (1-64 KiB, a tuning choice); wave g of G takes spans g, g+G, ...
-//    and streams each in 1 KiB steps: 64 lanes x 16 bytes, one 16-byte load per lane,
-//    the next three steps' loads already in flight.
+//  * Spans. The text is cut into spans of 2^span_log2 bytes (2-64 KiB, a tuning choice);
+//    wave g of G takes spans g, g+G, ... and streams each in 2 KiB steps: 64 lanes x 32
+//    bytes, two 16-byte buffer loads per lane, the next two steps' loads in flight.
 //  * LDS prefilter. No pattern is shorter than min_len, so a start can only match if its
-//    first k = min(min_len, kmax) symbols begin some pattern. Each lane tests its 16
-//    starts against an LDS bitmap: a hashed k-gram filter or the root image itself. A
-//    clear bit proves there is no match there; a set bit sends the start to the walk,
-//    which decides exactly.
+//    first symbols begin some pattern. Bytes with every pattern four or longer take the
+//    sampled form: every second start is probed with its 3-gram (a pattern starting
+//    there or one byte earlier has that 3-gram at offset 0 or 1), and the starts that
+//    pass are checked 64 at a time against a two-probe 4-gram filter, reading their
+//    bytes back from the step staged in LDS. Other sets probe every start's k-gram in a
+//    two-probe Bloom filter, or the root image itself. A clear bit proves there is no
+//    match there; a start that passes is walked, which decides exactly.
 //  * Root image. The top D trie levels are folded into one direct-indexed bitmap over
 //    D-symbol keys (lexicographic), with a rank per 32-bit word: the rank of a key is
 //    its depth-D node's breadth-first index minus the first depth-D index, i.e. Eq. 1's
@@ -23,15 +26,16 @@
 //    time, one per lane, mostly at the end of the span so walks seldom stall the stream
 //    of text loads. Walks read nodes and text through L2.
 //  * Per span the kernel stores the match count and one record per matching start
-//    (start, first terminal node, number of terminals), up to span / 64 records (at
-//    least 256).
+//    (start, and the id, or the first terminal node, or nothing), up to span / 64
+//    records (at least 256).
 //
-// Placement kernel (place_emit): blocks of kBlockSpans spans, taken by ticket. A block
-// sums its spans' counts, finds its output offset by decoupled look-back over earlier
-// blocks, and writes every match key at its final place from the records, so the
-// output is sorted by (start, id) with no global sort. A start that passed several
-// terminals, and any start of a span with more matching starts than records, is walked
-// again from the root in HBM.
+// Placement kernel (place_emit): blocks of kBlockSpans spans. A block finds its output
+// offset (the matches of all spans before it: summed by the block itself up to
+// kDirectMaxSpans spans, else by decoupled look-back over earlier blocks taken by
+// ticket) and writes every match key at its final place from the records, so the output
+// is sorted by (start, id) with no global sort. A start that passed several terminals,
+// and any start of a span with more matching starts than records, is walked again in
+// HBM.
 #include <mutex>
 
 #include "kernels.h"
