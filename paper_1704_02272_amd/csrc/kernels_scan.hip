@@ -72,6 +72,14 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
     return v;
 }
 
+// (m << 2) | b as one instruction: written out so the compiler keeps one shift-or per
+// bit instead of regrouping the chain into separate shifts and three-way ors.
+__device__ __forceinline__ uint32_t shl2_or(uint32_t m, uint32_t b) {
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, 2, %2" : "=v"(r) : "v"(m), "v"(b));
+    return r;
+}
+
 // Value of lane + 1 (lane 63 gets 0).
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
     return __builtin_amdgcn_update_dpp(0u, v, kDppWaveShl1, 0xf, 0xf, false);
@@ -428,12 +436,15 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
             // sampled: probe the 3-gram at every odd start j; a pattern (four bytes or
             // more) starting at j or j-1 puts its 3-gram at offset 0 or 1 there. The
             // mask holds the odd starts that pass: candidates, each standing for the
-            // starts j-1 and j, which the wave then checks 64 at a time (check_batch).
+            // starts j-1 and j, which the lane then checks (sample_step).
+            // bits gathered two positions at a time (one shift-or each), then moved up
+            // by one to their odd positions
 #pragma unroll
             for (int j = 15; j >= 1; j -= 2) {
                 const uint32_t x = __builtin_amdgcn_alignbyte(d[(j >> 2) + 1], d[j >> 2], j & 3);
-                mask |= probe3(img, x) << j;
+                mask = shl2_or(mask, probe3(img, x));
             }
+            mask <<= 1;
         } else if (FM == FM_GEN) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
             const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : (1u << (8 * t.filter_k)) - 1u;
@@ -526,8 +537,6 @@ struct Scanner {
     uint32_t n_packets;
     SpanOut so;
     uint16_t *q;  // survivor queue (span-local starts), kQ entries
-    uint16_t *cq; // sampled prefilter: candidate list (step-local odd starts), kCCap entries
-    uint8_t *stg; // sampled prefilter: this wave's staged step (kStageBytes)
     bool aligned;
 
     // A lane's bytes of one step: kLaneBytes (16 or 32) consecutive text bytes, with the
@@ -659,87 +668,69 @@ struct Scanner {
         push(q, S.qlen, kQ, m, sl0, [&] { drain(S); });
     }
 
-    // Sampled prefilter: check `cnt` listed candidates from cq[first], one per lane. A
-    // candidate j stands for the starts j-1 and j; each start's 4-gram, read from the
-    // staged step, is tested against the two-probe filter, and the starts that pass join
-    // the survivor queue, in position order.
-    __device__ __forceinline__ void check_batch(SpanState &S, uint64_t step, uint32_t first, uint32_t cnt) {
-        const uint32_t lane = lane_id();
-        const bool on = lane < cnt;
-        const uint32_t j = on ? cq[first + lane] : 1u;  // odd: bytes j-1 .. j+3 lie in two words
-        const uint32_t *st = reinterpret_cast<const uint32_t *>(stg) + ((j - 1) >> 2);
-        const uint32_t w0 = st[0], w1 = st[1];
-        const uint32_t k0 = __builtin_amdgcn_alignbyte(w1, w0, (j - 1) & 3u);
-        const uint32_t k1 = __builtin_amdgcn_alignbyte(w1, w0, j & 3u);
-        uint32_t p0 = probe4s_first(W.img, k0), p1 = probe4s_first(W.img, k1);
-        if (p0 | p1) {  // few pass the first probe: the second only for them
-            p0 &= probe4s_second(W.img, k0);
-            p1 &= probe4s_second(W.img, k1);
-        }
-        const uint64_t s0 = step + j - 1;
-        p0 &= (uint32_t)(on && s0 < S.top);
-        p1 &= (uint32_t)(on && s0 + 1 < S.top);
-        const uint64_t b0 = __ballot(p0 != 0), b1 = __ballot(p1 != 0);
-        if (!(b0 | b1)) return;
-        const uint32_t tot = (uint32_t)(__builtin_popcountll(b0) + __builtin_popcountll(b1));
-        if (S.qlen + tot > kQ) drain(S);  // now qlen < 64, and tot <= 128
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b0 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b0, 0u)) +
-                               __builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
-        const uint32_t at = S.qlen + below;
-        const uint32_t sl = (uint32_t)(s0 - S.a);
-        if (p0) q[at] = (uint16_t)sl;
-        if (p1) q[at + p0] = (uint16_t)(sl + 1);
-        S.qlen += tot;
-        __builtin_amdgcn_wave_barrier();
+    // The two words holding bytes j-1 .. j+3 of a lane's step bytes d[0..8] (j odd, so
+    // j-1 is even and the five bytes never span three words): d[q], d[q+1] with
+    // q = (j-1) >> 2, picked by a select tree on the bits of q (a register cannot be
+    // indexed by a value that differs between lanes).
+    __device__ __forceinline__ static void window2(const uint32_t (&d)[9], uint32_t j, uint32_t &lo, uint32_t &hi) {
+        const uint32_t q = (j - 1) >> 2;
+        const bool b2 = (q & 4u) != 0, b1 = (q & 2u) != 0, b0 = (q & 1u) != 0;
+        const uint32_t e0 = b2 ? d[4] : d[0], e1 = b2 ? d[5] : d[1], e2 = b2 ? d[6] : d[2], e3 = b2 ? d[7] : d[3];
+        const uint32_t f3 = b2 ? d[8] : d[4];
+        const uint32_t g0 = b1 ? e2 : e0, g1 = b1 ? e3 : e1, h1 = b1 ? f3 : e2;
+        lo = b0 ? g1 : g0;
+        hi = b0 ? h1 : g1;
     }
 
-    // Sampled prefilter, one step: m holds this lane's candidates (bit j: start
-    // step + kLaneBytes * lane + j, j odd). The step's bytes go to the wave's staging
-    // area, the candidates to the list in position order, kCCap at a time, each window
-    // checked 64 at a time before the next is listed.
+    // Both 4-gram probes of the starts j-1 and j (bits j-1 and j of the result).
+    __device__ __forceinline__ uint32_t check2(const uint32_t (&d)[9], uint32_t j) const {
+        uint32_t lo, hi;
+        window2(d, j, lo, hi);
+        const uint32_t k0 = __builtin_amdgcn_alignbyte(hi, lo, (j - 1) & 3u);
+        const uint32_t k1 = __builtin_amdgcn_alignbyte(hi, lo, j & 3u);
+        const uint32_t p0 = probe4s_first(W.img, k0) & probe4s_second(W.img, k0);
+        const uint32_t p1 = probe4s_first(W.img, k1) & probe4s_second(W.img, k1);
+        return (p0 << (j - 1)) | (p1 << j);
+    }
+
+    // Sampled prefilter, one step: m holds this lane's candidates (bit j, j odd: the
+    // starts j-1 and j of the lane's bytes). Each lane checks its own: the first two
+    // candidates of every lane together (all their LDS probes in flight at once), then
+    // any further ones (rare). Starts whose 4-gram passes join the survivor queue.
     __device__ __forceinline__ void sample_step(SpanState &S, uint64_t step, const Chunk &cur, uint32_t nd,
-                                                uint32_t m) {
+                                                uint32_t m, uint32_t sl0) {
+        static_assert(kLaneBytes == 32, "the sampled check reads a lane's 32 bytes");
         if (!__ballot(m != 0)) return;
-        const uint32_t lane = lane_id();
-#pragma unroll
-        for (uint32_t h = 0; h < kLaneBytes / 16; h++)
-            *reinterpret_cast<uint4 *>(stg + kLaneBytes * lane + 16 * h) = cur.v[h];
-        // the word after the lane's bytes: the next lane's first (the same value), and
-        // for the last lane the word after the step
-        *reinterpret_cast<uint32_t *>(stg + kLaneBytes * lane + kLaneBytes) = nd;
-        const uint32_t c = __builtin_popcount(m);
-        const uint32_t inc = wave_incl_scan(c);
-        const uint32_t tot = __builtin_amdgcn_readlane(inc, 63);
-        const uint32_t pos0 = kLaneBytes * lane;
-        for (uint32_t done = 0; done < tot; done += kCCap) {
-            const uint32_t w = tot - done < kCCap ? tot - done : kCCap;
-            uint32_t mm = m, k = inc - c - done;  // entry of this lane's first candidate in the window
-            __builtin_amdgcn_wave_barrier();
-            if (w == tot) {
-                while (mm) {
-                    const uint32_t j = __builtin_ctz(mm);
-                    mm &= mm - 1;
-                    cq[k++] = (uint16_t)(pos0 + j);
-                }
-            } else {  // entries outside the window wrap past w (unsigned) and are skipped
-                while (mm) {
-                    const uint32_t j = __builtin_ctz(mm);
-                    mm &= mm - 1;
-                    if (k < w) cq[k] = (uint16_t)(pos0 + j);
-                    k++;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-            for (uint32_t b = 0; b < w; b += 64) check_batch(S, step, b, w - b < 64 ? w - b : 64);
+        const uint32_t d[9] = {cur.v[0].x, cur.v[0].y, cur.v[0].z, cur.v[0].w,
+                               cur.v[1].x, cur.v[1].y, cur.v[1].z, cur.v[1].w, nd};
+        const uint32_t m2 = m & (m - 1), m3 = m2 & (m2 - 1);
+        uint32_t sm = 0;
+        if (m) {  // only lanes with candidates probe (fewer LDS bank conflicts)
+            const uint32_t sA = check2(d, (uint32_t)__builtin_ctz(m));
+            const uint32_t sB = check2(d, m2 ? (uint32_t)__builtin_ctz(m2) : 1u);
+            sm = sA | (m2 ? sB : 0u);
         }
-        __builtin_amdgcn_wave_barrier();
+        for (uint32_t r = m3; __ballot(r != 0);) {
+            const uint32_t j = r ? (uint32_t)__builtin_ctz(r) : 1u;
+            const uint32_t s = check2(d, j);
+            sm |= r ? s : 0u;
+            r &= r - 1;
+        }
+        // the span's last step: keep starts below top
+        if (step + kStep > S.top) {
+            const uint64_t s0 = S.a + sl0;
+            if (s0 + kLaneBytes > S.top) sm &= s0 >= S.top ? 0u : (uint32_t)((1ull << (uint32_t)(S.top - s0)) - 1ull);
+        }
+        take(S, sm, sl0);
     }
 
-    // One step's prefilter mask: candidates (sampled prefilter) or survivors.
-    __device__ __forceinline__ void take_mask(SpanState &S, uint64_t step, const Chunk &cur, uint32_t nd, uint32_t m,
-                                              uint32_t sl0) {
-        if (kSampled)
-            sample_step(S, step, cur, nd, m);
+    // One step's prefilter mask: candidates (sampled prefilter, checked here) or survivors.
+    __device__ __forceinline__ void step_body(SpanState &S, uint64_t step, uint64_t top, const Chunk &cur, uint32_t nd,
+                                              uint32_t nc) {
+        uint32_t sl0;
+        const uint32_t m = mask_step(S, step, top, cur, nd, nc, &sl0);
+        if constexpr (kSampled)
+            sample_step(S, step, cur, nd, m, sl0);
         else
             take(S, m, sl0);
     }
@@ -820,14 +811,16 @@ struct Scanner {
 #pragma unroll
             for (uint32_t i = 0; i < kPrefetch; i++)
                 buf[i] = chunk_buffer(rs, loff, (uint32_t)(step + i * kStep < lastst ? step + i * kStep : lastst));
+            const uint32_t last32 = (uint32_t)lastst;  // the text is below 4 GiB
             for (; step < hiR; step += kStep) {
-                const uint64_t ak = step + kPrefetch * kStep < lastst ? step + kPrefetch * kStep : lastst;
-                const Chunk nxk = chunk_buffer(rs, loff, (uint32_t)ak);
+                // kPrefetch steps ahead, clamped to the last step (32-bit scalar arithmetic;
+                // step <= lastst here, so the difference does not wrap)
+                const uint32_t st32 = (uint32_t)step;
+                const uint32_t ak = last32 - st32 > kPrefetch * kStep ? st32 + kPrefetch * kStep : last32;
+                const Chunk nxk = chunk_buffer(rs, loff, ak);
                 uint32_t nd, nc;
                 next_lane_head(buf[0], buf[1 % kPrefetch], step == lastst, after, &nd, &nc);
-                uint32_t sl0;
-                const uint32_t m = mask_step(S, step, top, buf[0], nd, nc, &sl0);
-                take_mask(S, step, buf[0], nd, m, sl0);
+                step_body(S, step, top, buf[0], nd, nc);
 #pragma unroll
                 for (uint32_t i = 0; i + 1 < kPrefetch; i++) buf[i] = buf[i + 1];
                 buf[kPrefetch - 1] = nxk;
@@ -842,9 +835,7 @@ struct Scanner {
                 const Chunk nx2 = chunk_guarded(step + 2 * kStep + kLaneBytes * lane, ld);
                 uint32_t nd, nc;
                 next_lane_head(cur, nx1, false, make_uint4(0u, 0u, 0u, 0u), &nd, &nc);
-                uint32_t sl0;
-                const uint32_t m = mask_step(S, step, top, cur, nd, nc, &sl0);
-                take_mask(S, step, cur, nd, m, sl0);
+                step_body(S, step, top, cur, nd, nc);
                 cur = nx1;
                 nx1 = nx2;
             }
@@ -915,10 +906,8 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     // load offsets) then stays in scalar registers
     const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint16_t *wq = reinterpret_cast<uint16_t *>(img + L::queues) + wave * L::qcap;
-    uint16_t *wc = reinterpret_cast<uint16_t *>(img + L::cands) + wave * kCCap;      // sampled only
-    uint8_t *ws = reinterpret_cast<uint8_t *>(img + L::stage) + wave * kStageBytes;  // sampled only
     Scanner<LAYOUT, PACK2, SEG, FM> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
-                                   offsets, n_packets, so, wq, wc, ws, (((uintptr_t)text) & 15) == 0};
+                                   offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0};
     const uint32_t waves = gridDim.x * kWaves;
     for (uint32_t span = blockIdx.x * kWaves + wave; span < n_spans; span += waves) {
         SpanState S{(uint64_t)span << span_log2, span, 0, 0, kNone, 0};

@@ -61,12 +61,11 @@ static_assert((1u << kStepLog2) == kStep, "step length is a power of two");
 //             two-probe Bloom filter over k-gram keys, every start probed; the short
 //             bitmap holds the D-grams of patterns shorter than k
 //   sampled   [second-probe part: 2^16 bits][first-probe part: 2^17 bits][3-gram part: 2^19 bits]
-//             [text staging: one step a wave][root bitmap][rank table]
-//             [survivor queues, 512 entries a wave][candidate lists, kCCap entries a wave]
+//             [root bitmap][rank table][survivor queues, 512 entries a wave]
 //             patterns of four or more bytes and k = 4: only every second start is
 //             probed, with the 3-gram there against the 3-grams at offsets 0 and 1 of
 //             every pattern; the two starts it stands for are then checked against the
-//             two-probe Bloom filter over 4-grams, read from the staged step.
+//             two-probe Bloom filter over 4-grams, by the lane that holds their bytes.
 // The builder's image holds the filter words (copied to offset 0), then the root bitmap,
 // the rank table and the short bitmap (copied to their places).
 constexpr uint32_t kMaxFilterLog2 = PFAC_FILTER_LOG2;    // general first-probe part: 2^19 bits
@@ -87,10 +86,6 @@ static_assert(kSampledWords % 4 == 0 && kGeneralWords % 4 == 0, "filters copy in
 constexpr uint32_t kFilterMul3 = 0x9E3779u;  // 24-bit multiplier of the 3-gram hash
 constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
-constexpr uint32_t kStageBytes = kStep + 16;              // sampled: a step and the word after it
-static_assert(kStageBytes % 16 == 0, "staged steps stay 16-byte aligned");
-constexpr uint32_t kCCap = 128;                           // sampled: candidates listed at a time
-static_assert(kCCap >= 64 && kCCap % 64 == 0, "a candidate window is whole batches");
 
 template <bool SAMPLED>
 struct Lds;
@@ -101,22 +96,18 @@ struct Lds<false> {
     static constexpr uint32_t rank = root + kRootWordsMax;
     static constexpr uint32_t qcap = PFAC_QCAP;
     static constexpr uint32_t queues = rank + kRankWordsMax;
-    static constexpr uint32_t stage = 0, cands = 0;  // none
     static constexpr uint32_t words = queues + kWaves * qcap / 2;
 };
 template <>
 struct Lds<true> {
-    static constexpr uint32_t stage = kSampledWords;
-    static constexpr uint32_t root = stage + kWaves * kStageBytes / 4;
+    static constexpr uint32_t root = kSampledWords;
     static constexpr uint32_t rank = root + kRootWordsMax;
     static constexpr uint32_t shrt = 0;  // none: no pattern is shorter than k
     static constexpr uint32_t qcap = PFAC_QCAP;
     static constexpr uint32_t queues = rank + kRankWordsMax;
-    static constexpr uint32_t cands = queues + kWaves * qcap / 2;
-    static constexpr uint32_t words = cands + kWaves * kCCap / 2;
+    static constexpr uint32_t words = queues + kWaves * qcap / 2;
 };
 static_assert(Lds<false>::qcap >= 128 && Lds<false>::qcap % 8 == 0, "a queue holds two walk batches");
-static_assert(Lds<true>::qcap >= 192, "a queue below 64 entries takes a checked batch (up to 128)");
 static_assert(Lds<false>::words * 4 <= 160 * 1024 && Lds<true>::words * 4 <= 160 * 1024, "LDS of one CU");
 
 // Per-span results of the count kernel (device memory, owned by a workspace).
