@@ -13,9 +13,9 @@
 //  * LDS prefilter. No pattern is shorter than min_len, so a start can only match if its
 //    first symbols begin some pattern. Bytes with every pattern four or longer take the
 //    sampled form: every second start is probed with its 3-gram (a pattern starting
-//    there or one byte earlier has that 3-gram at offset 0 or 1), and the starts that
-//    pass are checked 64 at a time against a two-probe 4-gram filter, reading their
-//    bytes back from the step staged in LDS. Other sets probe every start's k-gram in a
+//    there or one byte earlier has that 3-gram at offset 0 or 1), and the lane holding
+//    the bytes of a start that passes checks its 4-grams against a two-probe 4-gram
+//    filter. Other sets probe every start's k-gram in a
 //    two-probe Bloom filter, or the root image itself. A clear bit proves there is no
 //    match there; a start that passes is walked, which decides exactly.
 //  * Root image. The top D trie levels are folded into one direct-indexed bitmap over
