@@ -394,15 +394,15 @@ __device__ __forceinline__ uint32_t probe3(const uint32_t *img, uint32_t x) {
                                                           ((h >> 16) & ((kS3Words - 1u) << 2)));
     return __builtin_amdgcn_ubfe(w, x, 1);
 }
-__device__ __forceinline__ uint32_t probe4s_first(const uint32_t *img, uint32_t key) {
-    const uint32_t o1 = ((s1_hash(key) >> 16) & ((kS1Words - 1u) << 2)) + kLdsS1 * 4;
-    const uint32_t w1 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o1);
-    return __builtin_amdgcn_ubfe(w1, key, 1);
-}
-__device__ __forceinline__ uint32_t probe4s_second(const uint32_t *img, uint32_t key) {
-    const uint32_t o2 = ((s2_hash(key) >> 16) & ((kS2Words - 1u) << 2)) + kLdsS2 * 4;
-    const uint32_t w2 = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(img) + o2);
-    return __builtin_amdgcn_ubfe(w2, key >> 24, 1);
+// Both 4-gram probes of one key, given key >> 8 as well (bytes 1..3: probe 1's hash
+// input, and its low five bits are probe 2's bit).
+__device__ __forceinline__ uint32_t probe4s(const uint32_t *img, uint32_t key, uint32_t key_hi) {
+    const uint8_t *b = reinterpret_cast<const uint8_t *>(img);
+    const uint32_t o1 = (((key_hi & 0xffffffu) * kS1Mul) >> 16) & ((kS1Words - 1u) << 2);
+    const uint32_t o2 = (s2_hash(key) >> 16) & ((kS2Words - 1u) << 2);
+    const uint32_t w1 = *reinterpret_cast<const uint32_t *>(b + kLdsS1 * 4 + o1);
+    const uint32_t w2 = *reinterpret_cast<const uint32_t *>(b + kLdsS2 * 4 + o2);
+    return __builtin_amdgcn_ubfe(w1, key, 1) & __builtin_amdgcn_ubfe(w2, key_hi, 1);
 }
 
 // Four bytes starting at byte j (0..15) of the 20 bytes v, d4 (little-endian words).
@@ -686,11 +686,13 @@ struct Scanner {
     __device__ __forceinline__ uint32_t check2(const uint32_t (&d)[9], uint32_t j) const {
         uint32_t lo, hi;
         window2(d, j, lo, hi);
+        // k0 = bytes j-1..j+2, k1 = bytes j..j+3: k0 >> 8 equals k1 in the 24 bits a
+        // 24-bit multiply reads (and in its low byte), so k1 stands in for it
         const uint32_t k0 = __builtin_amdgcn_alignbyte(hi, lo, (j - 1) & 3u);
         const uint32_t k1 = __builtin_amdgcn_alignbyte(hi, lo, j & 3u);
-        const uint32_t p0 = probe4s_first(W.img, k0) & probe4s_second(W.img, k0);
-        const uint32_t p1 = probe4s_first(W.img, k1) & probe4s_second(W.img, k1);
-        return (p0 << (j - 1)) | (p1 << j);
+        const uint32_t p0 = probe4s(W.img, k0, k1);
+        const uint32_t p1 = probe4s(W.img, k1, k1 >> 8);
+        return ((p1 << 1) | p0) << (j - 1);
     }
 
     // Sampled prefilter, one step: m holds this lane's candidates (bit j, j odd: the
@@ -706,9 +708,8 @@ struct Scanner {
         const uint32_t m2 = m & (m - 1), m3 = m2 & (m2 - 1);
         uint32_t sm = 0;
         if (m) {  // only lanes with candidates probe (fewer LDS bank conflicts)
-            const uint32_t sA = check2(d, (uint32_t)__builtin_ctz(m));
-            const uint32_t sB = check2(d, m2 ? (uint32_t)__builtin_ctz(m2) : 1u);
-            sm = sA | (m2 ? sB : 0u);
+            sm = check2(d, (uint32_t)__builtin_ctz(m));
+            if (m2) sm |= check2(d, (uint32_t)__builtin_ctz(m2));
         }
         for (uint32_t r = m3; __ballot(r != 0);) {
             const uint32_t j = r ? (uint32_t)__builtin_ctz(r) : 1u;

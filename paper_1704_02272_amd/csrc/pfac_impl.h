@@ -104,13 +104,13 @@ inline void filter3_insert(uint32_t *F, uint32_t key, uint32_t mul3, uint32_t of
 // Two-probe filter over 4-gram keys of the sampled prefilter, hashed with 24-bit products
 // (full-rate multiplies on the GPU). Probe 1: word from bits 18.. of bytes 1..3 * kS1Mul,
 // bit = the low five bits of byte 0. Probe 2: word from bits 18.. of bytes 0..2 * kS2Mul,
-// bit = the low five bits of byte 3. The builder and the kernels must agree bit for bit.
+// bit = the low five bits of byte 1. The builder and the kernels must agree bit for bit.
 constexpr uint32_t kS1Mul = 0x9E3779u, kS2Mul = 0x85EBCBu;
 __host__ __device__ inline uint32_t s1_hash(uint32_t key) { return (key >> 8) * kS1Mul; }
 __host__ __device__ inline uint32_t s2_hash(uint32_t key) { return (key & 0xffffffu) * kS2Mul; }
 inline void filter4s_insert(uint32_t *F, uint32_t key, uint32_t o1, uint32_t w1, uint32_t o2, uint32_t w2) {
     F[o1 + ((s1_hash(key) >> 18) & (w1 - 1u))] |= 1u << (key & 31);
-    F[o2 + ((s2_hash(key) >> 18) & (w2 - 1u))] |= 1u << ((key >> 24) & 31);
+    F[o2 + ((s2_hash(key) >> 18) & (w2 - 1u))] |= 1u << ((key >> 8) & 31);
 }
 
 struct Workspace;  // per (device, stream) scratch, defined in the runtime
