@@ -673,8 +673,8 @@ struct Scanner {
     // q = (j-1) >> 2, picked by a select tree on the bits of q (a register cannot be
     // indexed by a value that differs between lanes).
     __device__ __forceinline__ static void window2(const uint32_t (&d)[9], uint32_t j, uint32_t &lo, uint32_t &hi) {
-        const uint32_t q = (j - 1) >> 2;
-        const bool b2 = (q & 4u) != 0, b1 = (q & 2u) != 0, b0 = (q & 1u) != 0;
+        // bits 2..4 of j are those of j-1 (j-1 is even); bit 4 as a compare
+        const bool b2 = j >= 16u, b1 = (j & 8u) != 0, b0 = (j & 4u) != 0;
         const uint32_t e0 = b2 ? d[4] : d[0], e1 = b2 ? d[5] : d[1], e2 = b2 ? d[6] : d[2], e3 = b2 ? d[7] : d[3];
         const uint32_t f3 = b2 ? d[8] : d[4];
         const uint32_t g0 = b1 ? e2 : e0, g1 = b1 ? e3 : e1, h1 = b1 ? f3 : e2;
@@ -718,7 +718,8 @@ struct Scanner {
             r &= r - 1;
         }
         // the span's last step: keep starts below top
-        if (step + kStep > S.top) {
+        // span-local and 32-bit (scalar); top can lie before the span start
+        if ((uint32_t)(step - S.a) + kStep > (S.top > S.a ? (uint32_t)(S.top - S.a) : 0u)) {
             const uint64_t s0 = S.a + sl0;
             if (s0 + kLaneBytes > S.top) sm &= s0 >= S.top ? 0u : (uint32_t)((1ull << (uint32_t)(S.top - s0)) - 1ull);
         }
@@ -767,7 +768,8 @@ struct Scanner {
         const uint32_t sl0 = (uint32_t)(step - S.a) + kLaneBytes * lane;  // span-local start of bit 0
         // last step: keep starts below top (a candidate j while j-1 is below it)
         const uint64_t cut = FM == FM_K4 && !PACK2 ? top + 1 : top;
-        if (step + kStep > cut) {
+        // span-local and 32-bit (scalar); cut can lie before the span start
+        if ((uint32_t)(step - S.a) + kStep > (cut > S.a ? (uint32_t)(cut - S.a) : 0u)) {
             const uint64_t s0 = S.a + sl0;
             if (s0 + kLaneBytes > cut) m &= s0 >= cut ? 0u : (uint32_t)((1ull << (uint32_t)(cut - s0)) - 1ull);
         }
