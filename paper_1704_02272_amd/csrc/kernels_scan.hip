@@ -418,14 +418,15 @@ __device__ __forceinline__ uint32_t probe_root(const uint32_t *root, uint32_t ke
     return __builtin_amdgcn_ubfe(root[key >> 5], key, 1);
 }
 
-// Survivor mask of this lane's 16 starts (bit j = start 16*lane + j of the step).
-// cur: this lane's 16 bytes; next_d0: the 4 bytes after them; c0/c1: two-bit codes of
-// this lane's and the next 16 bytes.
 // Prefilter forms, fixed per kernel instance: FM_K4 four-byte keys and no pattern shorter
 // than four (the sampled layout); FM_GEN any key length, with the short-pattern bitmap;
 // FM_ROOT no hashed filter (the root image's D-gram bitmap is the test).
 enum FilterMode : int { FM_K4 = 0, FM_GEN = 1, FM_ROOT = 2 };
 
+// Prefilter mask of 16 starts of a lane (bit j = the start at byte j of cur): the
+// survivors, or for FM_K4 the candidates (odd j only; see sample_step). cur: the 16
+// bytes; next_d0: the 4 bytes after them; c0/c1: two-bit codes of these and the next
+// 16 bytes.
 template <bool PACK2, int FM>
 __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_t *img, uint4 cur,
                                                 uint32_t next_d0, uint32_t c0, uint32_t c1) {
