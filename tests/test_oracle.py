@@ -233,3 +233,109 @@ def test_pins_catch_planted_mistakes_in_python_oracle(monkeypatch):
     pats = [p.encode() for p in g["patterns"]]
     off, bm = trie.paper_layout(pats, 256)
     assert trie.child(off, bm, 1, ord("D")) != g["node_of_D"]
+
+
+# ------------------------------------------------------------------------ packet batches
+def _batch_cases():
+    out = []
+    for c in _load("packet_batches.json")["cases"]:
+        data = b"".join(bytes.fromhex(p) for p in c["data_parts"])
+        offs = np.array(c["offsets"], dtype=np.uint64)
+        # the parts are the packets: the offsets must cut the data at their ends
+        ends = np.cumsum([0] + [len(bytes.fromhex(p)) for p in c["data_parts"]])
+        assert list(ends) == c["offsets"]
+        out.append((c["name"], c["alphabet"], [bytes.fromhex(p) for p in c["patterns"]],
+                    data, offs, [tuple(x) for x in c["expected"]]))
+    return out
+
+
+def _random_batch(rng, sigma, n_pk, max_pk):
+    sizes = rng.integers(0, max_pk + 1, size=n_pk)
+    sizes[rng.random(n_pk) < 0.2] = 0          # empty packets
+    sizes[rng.random(n_pk) < 0.1] = 1          # one-byte packets
+    offs = np.zeros(n_pk + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    data = rng.integers(0, sigma, size=int(offs[-1])).astype(np.uint8)
+    return data, offs
+
+
+def _per_packet_literal(pats, data, offs):
+    """Each packet matched alone with the plain definition, starts moved by the
+    packet's first byte: written out here, independent of both oracle helpers."""
+    out = []
+    raw = bytes(data)
+    for i in range(len(offs) - 1):
+        a, b = int(offs[i]), int(offs[i + 1])
+        out.extend((a + s, j) for s, j in literal.match_set(pats, raw[a:b]))
+    return out
+
+
+@pytest.mark.parametrize("case", _batch_cases(), ids=lambda c: c[0])
+def test_packet_batch_hand_cases(case):
+    name, alphabet, pats, data, offs, expected = case
+    arr = np.frombuffer(data, dtype=np.uint8)
+    assert _pairs(native.AhoCorasick(pats, alphabet).scan_packets(arr, offs)) == expected
+    assert literal.match_set_packets(pats, data, offs) == expected
+    assert literal.keys(expected) == [(s << 32) | j for s, j in expected]
+
+
+def test_packet_batch_random_against_per_packet_definition():
+    rng = np.random.default_rng(21)
+    for trial in range(120):
+        sigma = int(rng.choice([2, 4, 256]))
+        pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(1, 7))).astype(np.uint8))
+                for _ in range(int(rng.integers(1, 25)))]
+        data, offs = _random_batch(rng, sigma, int(rng.integers(1, 40)), int(rng.integers(1, 60)))
+        want = _per_packet_literal(pats, data, offs)
+        assert _pairs(native.AhoCorasick(pats, sigma).scan_packets(data, offs)) == want
+        assert literal.match_set_packets(pats, data.tobytes(), offs) == want
+        # brute force over each packet, keys shifted by the packet's first byte
+        parts = [native.brute(pats, data[int(offs[i]):int(offs[i + 1])]) + np.uint64(int(offs[i]) << 32)
+                 for i in range(len(offs) - 1)]
+        got = np.concatenate(parts) if parts else np.zeros(0, np.uint64)
+        assert _pairs(np.sort(got)) == want
+
+
+def test_keys_hand_values():
+    """(s << 32) | j: start in the high word, id in the low word, so numeric order is
+    (start, id) order."""
+    assert literal.keys([(0, 5), (1, 2), (1, 7), (4294967295, 4294967295)]) == [
+        5, 4294967298, 4294967303, 18446744073709551615]
+    assert literal.keys([]) == []
+    k = literal.keys([(3, 9), (2, 100), (3, 1)])
+    assert sorted(k) == literal.keys([(2, 100), (3, 1), (3, 9)])
+
+
+def test_packet_pins_catch_planted_mistakes():
+    """Copies of the packet scan with a plausible mistake each fail a pin above."""
+    cases = _batch_cases()
+
+    class ByIndex(native.AhoCorasick):       # shifts starts by the packet index
+        def scan_packets(self, data, offsets, threads=0):
+            parts = []
+            for i in range(len(offsets) - 1):
+                k = self.scan(np.asarray(data)[int(offsets[i]):int(offsets[i + 1])], threads=1)
+                parts.append(k + np.uint64(i << 32))
+            return np.concatenate(parts) if parts else np.zeros(0, np.uint64)
+
+    class DropLast(native.AhoCorasick):      # forgets the last packet
+        def scan_packets(self, data, offsets, threads=0):
+            return super().scan_packets(data, offsets[:-1], threads)
+
+    class Concatenated(native.AhoCorasick):  # scans the batch as one text
+        def scan_packets(self, data, offsets, threads=0):
+            return self.scan(np.asarray(data)[:int(offsets[-1])])
+
+    for bad in (ByIndex, DropLast, Concatenated):
+        caught = any(_pairs(bad(p, a).scan_packets(np.frombuffer(d, np.uint8), o)) != e
+                     for _, a, p, d, o, e in cases)
+        assert caught, bad.__name__
+
+    def literal_no_shift(patterns, data, offsets):   # forgets the packet base
+        out = []
+        for i in range(len(offsets) - 1):
+            a, b = int(offsets[i]), int(offsets[i + 1])
+            out.extend(literal.match_set(patterns, bytes(data)[a:b]))
+        return sorted(out)
+
+    assert any(literal_no_shift(p, d, o) != e for _, _, p, d, o, e in cases)
