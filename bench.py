@@ -100,9 +100,28 @@ def cpu_baseline(w, budget_s: float):
         t_total += time.perf_counter() - t0
         reps += 1
     gbit = 8.0 * n * reps / t_total / 1e9
+    # one thread on a leading slice of the same text (about a second of work)
+    n1 = min(n, 1 << 26)
+    t0 = time.perf_counter()
+    ac.scan(w.text[:n1], threads=1)
+    t1 = time.perf_counter() - t0
     return {"value": round(gbit, 3), "unit": "Gbit/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": round(8.0 * n1 / t1 / 1e9, 3), "unit": "Gbit/s",
+                           "sample": "first %d bytes of the text, one scan" % n1},
             "sample": "whole %s text (%d bytes) x %d scans, %.1f s, textbook Aho-Corasick "
                       "with OpenMP chunks" % (w.name, n, reps, t_total)}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (as /proc/cpuinfo states it)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_packets(args, w):
@@ -232,6 +251,8 @@ def bench_serving(args):
     give per-packet p50/p99 latency and the achieved rate."""
     import threading
 
+    import numpy as np
+
     import paper_1704_02272_amd.pfac as pfac
     from paper_1704_02272_amd import workloads as W
 
@@ -251,13 +272,24 @@ def bench_serving(args):
     done = {"n": 0, "matches": 0, "bad": 0}
     n_total = len(ptrs)
     stop = threading.Event()
+    # a sample of requests, evenly spread over the stream, whose keys are kept and
+    # checked against the oracle after the run
+    n_verify = min(args.verify, n_total)
+    verify_idx = set(np.linspace(0, n_total - 1, n_verify).astype(int).tolist()) if n_verify else set()
+    ticket_of = {}
+    kept = {}
+    phases = []  # per request: queueing (launch - arrival), service (done - launch), total
 
     def drain():
         while done["n"] < n_total and not stop.is_set():
-            for r in srv.poll(timeout_us=50000, with_keys=False):
+            for r in srv.poll(timeout_us=50000, with_keys=bool(verify_idx)):
                 done["n"] += 1
                 done["matches"] += r["n_matches"]
                 done["bad"] += r["status"] != 0
+                phases.append((r["launch_ns"] - r["arrival_ns"], r["done_ns"] - r["launch_ns"],
+                               r["done_ns"] - r["arrival_ns"]))
+                if r["ticket"] in ticket_of:
+                    kept[ticket_of[r["ticket"]]] = r["keys"]
 
     th = threading.Thread(target=drain, daemon=True)
     th.start()
@@ -272,6 +304,8 @@ def bench_serving(args):
                 busy += 1
             elif rc:
                 raise pfac.PfacError(rc, "pfac_server_submit")
+            elif i in verify_idx:
+                ticket_of[srv.last] = i
             i += 1
         if i < n_total:
             wait = (t0 + arr_ns[i] - time.monotonic_ns()) / 1e9
@@ -282,6 +316,17 @@ def bench_serving(args):
     st = srv.stats()
     srv.close()
     offered = 8.0 * sum(p[2] for p in ptrs) / (arr_ns[-1] / 1e9) / 1e9
+    # every request has the same number of packets, so per-request percentiles are the
+    # per-packet ones
+    ph = np.array(phases, dtype=np.float64).reshape(-1, 3) / 1e3
+    pct = (lambda col, q: round(float(np.percentile(ph[:, col], q)), 1) if len(ph) else None)
+    mism = None
+    if verify_idx:
+        from oracle import native
+        ac = native.AhoCorasick(w.patterns, w.alphabet)
+        mism = sum(not np.array_equal(kept.get(i, np.zeros(1, np.uint64) - 1),
+                                      ac.scan_packets(w.requests[i].data, w.requests[i].offsets))
+                   for i in sorted(verify_idx))
     out = {
         "metric": METRIC, "value": round(st["bytes_per_s"] * 8 / 1e9, 3), "unit": "Gbit/s", "n_gpus": 1,
         "steps": n_total, "warmup": 64, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
@@ -294,7 +339,10 @@ def bench_serving(args):
                     "p50_us": round(st["p50_ns"] / 1e3, 1), "p99_us": round(st["p99_ns"] / 1e3, 1),
                     "max_us": round(st["max_ns"] / 1e3, 1), "requests_done": done["n"],
                     "rejected_busy": busy, "failed": done["bad"], "batches": st["batches"],
-                    "mean_batch_kib": round(st["mean_batch_bytes"] / 1024, 1), "matches": done["matches"]},
+                    "mean_batch_kib": round(st["mean_batch_bytes"] / 1024, 1), "matches": done["matches"],
+                    "queue_us": {"p50": pct(0, 50), "p99": pct(0, 99), "max": pct(0, 100)},
+                    "service_us": {"p50": pct(1, 50), "p99": pct(1, 99), "max": pct(1, 100)},
+                    "verified_requests": len(verify_idx), "verify_mismatches": mism},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -315,6 +363,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="serving: batch slots")
     ap.add_argument("--batch-mib", type=int, default=8, help="serving: MiB per batch")
     ap.add_argument("--plant-every", type=int, default=0, help="serving: planted variant")
+    ap.add_argument("--verify", type=int, default=256,
+                    help="serving: requests (evenly spread) whose keys are checked against the oracle")
     ap.add_argument("--baseline-steps", type=int, default=3,
                     help="packets: timed passes of the per-packet baseline")
     ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host"],

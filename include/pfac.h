@@ -120,6 +120,37 @@ PFAC_API int pfac_export_paper_table(const pfac_automaton *a, uint32_t *offsets,
 PFAC_API int pfac_export_outputs(const pfac_automaton *a, uint32_t *first, uint64_t first_cap,
                         uint32_t *ids, uint64_t ids_cap);
 
+/* ------------------------------------------------------------------- saving
+ * pfac_save -- serialize the automaton into buf (host memory, cap bytes): the table of
+ * Section 3.1 (first-child offset and child bitmap of every node, breadth-first), the
+ * pattern ids ending at each node, the patterns and the tuning in force, behind a
+ * versioned header (magic, version, alphabet, node and pattern counts, longest and
+ * shortest pattern, payload size, 64-bit FNV-1a checksum). *size always receives the
+ * bytes needed; with buf NULL or cap too small nothing is written and the call returns
+ * PFAC_ECAPACITY. Device copies are not saved. Errors: PFAC_EINVAL (a or size NULL),
+ * PFAC_ECAPACITY. Host only.
+ *
+ * pfac_load -- rebuild an automaton from size bytes written by pfac_save. The blob is
+ * checked (header, sizes, checksum) and so is the table itself: it must be the
+ * breadth-first trie of the stored patterns (offsets of Section 3.1, every leaf ending a
+ * pattern, each pattern's Eq. 1 path ending at the node that lists it), so a loaded
+ * automaton equals the one pfac_build makes from the same patterns and scans only inside
+ * its arrays. The buffer may be freed on return. Errors: PFAC_EINVAL (out or buf NULL),
+ * PFAC_EFORMAT (truncated, corrupted or inconsistent blob; *out NULL), PFAC_ENOMEM.
+ * Host only. */
+PFAC_API int pfac_save(const pfac_automaton *a, uint8_t *buf, uint64_t cap, uint64_t *size);
+PFAC_API int pfac_load(const uint8_t *buf, uint64_t size, pfac_automaton **out);
+
+/* pfac_key_to_packet -- split n_keys batch keys (host memory, as written by the batch
+ * scans: global byte offset << 32 | pattern id) into the packet holding each start,
+ * the start within that packet and the pattern id, for packets given by h_offsets
+ * (n_pkts + 1 entries, non-decreasing, as passed to pfac_scan_batch; a match lies inside
+ * one packet, Section 2.2 applied per packet). Keys need not be sorted. Each output array
+ * holds n_keys entries (host memory). Errors: PFAC_EINVAL (NULL arrays with n_keys > 0,
+ * or a start outside [h_offsets[0], h_offsets[n_pkts])). Host only. */
+PFAC_API int pfac_key_to_packet(const uint64_t *h_keys, uint64_t n_keys, const uint64_t *h_offsets,
+                                uint32_t n_pkts, uint32_t *pkt, uint32_t *start, uint32_t *ids);
+
 /* ------------------------------------------------------------------- device
  * Copy the table to device `device` (HIP ordinal). Done implicitly by the first scan
  * on a device; the copy stays resident until pfac_destroy. Errors: PFAC_ENODEVICE (no

@@ -200,6 +200,56 @@ int rebuild_lds_image(pfac_automaton *a, uint32_t D, uint32_t K) {
     return PFAC_OK;
 }
 
+// Everything the scans need that follows from the trie and the patterns: the count of
+// terminal nodes, the node images of HBM, the path tails and the LDS image (with the
+// root depth and filter key the tuning asks for). Shared by building and loading.
+void finish_automaton(pfac_automaton *a) {
+    a->n_term = 0;
+    for (uint32_t q = 0; q < a->n_nodes; q++)
+        if (a->out_first[q + 1] > a->out_first[q]) a->n_term++;
+    a->dev_nodes.clear();
+    a->dev_bm.clear();
+    if (a->alphabet <= 32) {
+        a->layout = LAYOUT_NARROW;
+        a->nw = 0;
+        a->dev_nodes.resize(a->n_nodes);
+        for (uint32_t q = 0; q < a->n_nodes; q++) {
+            uint64_t w = a->bitmap[(size_t)q * a->nbw] & 0xffffffffull;
+            w |= (uint64_t)a->first_child[q] << 32;
+            if (a->out_first[q + 1] > a->out_first[q]) w |= kTermBit;
+            a->dev_nodes[q] = w;
+        }
+    } else {
+        a->layout = LAYOUT_WIDE;
+        a->nw = a->nbw <= 1 ? 1 : a->nbw <= 2 ? 2 : 4;
+        a->dev_nodes.resize(a->n_nodes);
+        a->dev_bm.assign((size_t)a->n_nodes * a->nw, 0);
+        for (uint32_t q = 0; q < a->n_nodes; q++) {
+            const uint64_t *b = &a->bitmap[(size_t)q * a->nbw];
+            uint64_t r1 = 0, r2 = 0, r3 = 0;
+            for (uint32_t w = 0; w < a->nbw; w++) a->dev_bm[(size_t)q * a->nw + w] = b[w];
+            if (a->nbw > 1) r1 = popc64(b[0]);
+            if (a->nbw > 2) r2 = r1 + popc64(b[1]);
+            if (a->nbw > 3) r3 = r2 + popc64(b[2]);
+            uint64_t m = a->first_child[q] | (r1 << 32) | (r2 << 40) | (r3 << 48);
+            if (a->out_first[q + 1] > a->out_first[q]) m |= kTermBit;
+            a->dev_nodes[q] = m;
+        }
+    }
+    build_tails(a);
+    DevTable &t = a->shape;
+    t = DevTable{};
+    t.alphabet = a->alphabet;
+    t.layout = a->layout;
+    t.nw_log2 = a->nw == 4 ? 2 : a->nw == 2 ? 1 : 0;
+    t.n_nodes = a->n_nodes;
+    t.min_len = a->min_len;
+    t.max_len = a->max_len;
+    std::vector<const uint8_t *> P(a->n_pats);
+    for (uint32_t j = 0; j < a->n_pats; j++) P[j] = a->pat_bytes.data() + a->pat_off[j];
+    build_lds_image(a, P, a->req_depth, a->req_k);
+}
+
 int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
                     uint32_t alphabet, pfac_automaton **out) {
     if (!out) return PFAC_EINVAL;
@@ -275,53 +325,12 @@ int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n
         }
         a->n_nodes = (uint32_t)a->first_child.size();
         while (a->depth_start.size() < (size_t)maxl + 3) a->depth_start.push_back(a->n_nodes);
-        a->n_term = 0;
-        for (uint32_t q = 0; q < a->n_nodes; q++)
-            if (a->out_first[q + 1] > a->out_first[q]) a->n_term++;
-
-        // device node images
-        if (alphabet <= 32) {
-            a->layout = LAYOUT_NARROW;
-            a->nw = 0;
-            a->dev_nodes.resize(a->n_nodes);
-            for (uint32_t q = 0; q < a->n_nodes; q++) {
-                uint64_t w = a->bitmap[(size_t)q * a->nbw] & 0xffffffffull;
-                w |= (uint64_t)a->first_child[q] << 32;
-                if (a->out_first[q + 1] > a->out_first[q]) w |= kTermBit;
-                a->dev_nodes[q] = w;
-            }
-        } else {
-            a->layout = LAYOUT_WIDE;
-            a->nw = a->nbw <= 1 ? 1 : a->nbw <= 2 ? 2 : 4;
-            a->dev_nodes.resize(a->n_nodes);
-            a->dev_bm.assign((size_t)a->n_nodes * a->nw, 0);
-            for (uint32_t q = 0; q < a->n_nodes; q++) {
-                const uint64_t *b = &a->bitmap[(size_t)q * a->nbw];
-                uint64_t r1 = 0, r2 = 0, r3 = 0;
-                for (uint32_t w = 0; w < a->nbw; w++) a->dev_bm[(size_t)q * a->nw + w] = b[w];
-                if (a->nbw > 1) r1 = popc64(b[0]);
-                if (a->nbw > 2) r2 = r1 + popc64(b[1]);
-                if (a->nbw > 3) r3 = r2 + popc64(b[2]);
-                uint64_t m = a->first_child[q] | (r1 << 32) | (r2 << 40) | (r3 << 48);
-                if (a->out_first[q + 1] > a->out_first[q]) m |= kTermBit;
-                a->dev_nodes[q] = m;
-            }
-        }
         a->pat_off.assign(n_pats + 1, 0);
         for (uint32_t j = 0; j < n_pats; j++) a->pat_off[j + 1] = a->pat_off[j] + lens[j];
         a->pat_bytes.resize(a->pat_off[n_pats]);
         for (uint32_t j = 0; j < n_pats; j++) memcpy(a->pat_bytes.data() + a->pat_off[j], P[j], lens[j]);
-        build_tails(a);
-        DevTable &t = a->shape;
-        t = DevTable{};
-        t.alphabet = alphabet;
-        t.layout = a->layout;
-        t.nw_log2 = a->nw == 4 ? 2 : a->nw == 2 ? 1 : 0;
-        t.n_nodes = a->n_nodes;
-        t.min_len = minl;
-        t.max_len = maxl;
-        build_lds_image(a, P, 0, 0);
         (void)total;
+        finish_automaton(a);
     } catch (const std::bad_alloc &) {
         delete a;
         return PFAC_ENOMEM;

@@ -163,4 +163,7 @@ void release_device_copies(pfac_automaton *a);
 // Rebuild the LDS image with root depth D and filter key length K (0 = the builder's
 // choice for either). PFAC_EINVAL when D or K is outside what the pattern set allows.
 int rebuild_lds_image(pfac_automaton *a, uint32_t D, uint32_t K);
+// Derive the device images (node words, path tails, LDS image) from the trie arrays,
+// the patterns and the requested root depth / filter key. Throws std::bad_alloc.
+void finish_automaton(pfac_automaton *a);
 }  // namespace pfac

@@ -112,6 +112,9 @@ def lib():
             "pfac_export_paper_table": (C.c_int, [VP, P32, C.c_uint64, P32, C.c_uint64]),
             "pfac_export_outputs": (C.c_int, [VP, P32, C.c_uint64, P32, C.c_uint64]),
             "pfac_upload": (C.c_int, [VP, C.c_int]),
+            "pfac_save": (C.c_int, [VP, P8, C.c_uint64, P64]),
+            "pfac_load": (C.c_int, [P8, C.c_uint64, C.POINTER(VP)]),
+            "pfac_key_to_packet": (C.c_int, [P64, C.c_uint64, P64, C.c_uint32, P32, P32, P32]),
             "pfac_scan_async": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
             "pfac_scan": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, P64, VP]),
             "pfac_scan_batch_async": (C.c_int, [VP, VP, VP, C.c_uint32, C.c_uint64, VP, C.c_uint64,
@@ -393,15 +396,41 @@ def pfac_graph_create(a: Automaton, data, offsets, keys, count, sizes, stream) -
     return Graph(h.value, (data, offsets, keys, count, sizes, a))
 
 
-def key_to_packet(keys: np.ndarray, offsets: np.ndarray):
-    """Host helper: (packet index, start within packet, pattern id) of uint64 keys from a
-    batch scan, by an upper bound of each start over the packet offsets."""
-    keys = np.asarray(keys, dtype=np.uint64)
-    starts = (keys >> np.uint64(32)).astype(np.int64)
-    ids = (keys & np.uint64(0xFFFFFFFF)).astype(np.int64)
-    offs = np.asarray(offsets, dtype=np.int64)
-    pk = np.searchsorted(offs, starts, side="right") - 1
-    return pk, starts - offs[pk], ids
+def pfac_key_to_packet(keys, offsets):
+    """(packet index, start within packet, pattern id) of uint64 batch keys (host numpy)
+    for packets given by ``offsets`` (uint64, n_pkts + 1), as three uint32 arrays."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = len(keys)
+    pk, st, ids = (np.zeros(max(n, 1), dtype=np.uint32) for _ in range(3))
+    P32, P64 = C.POINTER(C.c_uint32), C.POINTER(C.c_uint64)
+    rc = lib().pfac_key_to_packet(keys.ctypes.data_as(P64), n, offs.ctypes.data_as(P64), len(offs) - 1,
+                                  pk.ctypes.data_as(P32), st.ctypes.data_as(P32), ids.ctypes.data_as(P32))
+    _check(rc, "pfac_key_to_packet")
+    return pk[:n], st[:n], ids[:n]
+
+
+def pfac_save(a: Automaton) -> bytes:
+    """The automaton serialized by the library (see ``pfac_save`` in pfac.h)."""
+    size = C.c_uint64(0)
+    rc = lib().pfac_save(a.handle, None, 0, C.byref(size))
+    if rc not in (PFAC_OK, PFAC_ECAPACITY):
+        _check(rc, "pfac_save")
+    buf = np.zeros(int(size.value), dtype=np.uint8)
+    _check(lib().pfac_save(a.handle, buf.ctypes.data_as(C.POINTER(C.c_uint8)), len(buf), C.byref(size)),
+           "pfac_save")
+    return buf.tobytes()
+
+
+def pfac_load(blob) -> Automaton:
+    """An automaton rebuilt by the library from bytes written by ``pfac_save``."""
+    buf = np.frombuffer(bytes(blob), dtype=np.uint8)
+    h = C.c_void_p()
+    arr = buf if len(buf) else np.zeros(1, dtype=np.uint8)
+    _check(lib().pfac_load(arr.ctypes.data_as(C.POINTER(C.c_uint8)), len(buf), C.byref(h)), "pfac_load")
+    a = Automaton(h.value, 0)
+    a.max_len = pfac_table_info(a)["max_len"]
+    return a
 
 
 def pfac_scan_host(a: Automaton, text, chunk_bytes: int = 0) -> np.ndarray:

@@ -115,14 +115,162 @@ def test_empty_pattern_set():
     assert info["n_nodes"] == 1 and info["n_patterns"] == 0
 
 
-def test_key_to_packet_host_helper():
+def test_key_to_packet():
     # packets "a" | "bc" | "" | "ab" at offsets 0, 1, 3, 3; keys (start << 32) | id
     offsets = np.array([0, 1, 3, 3, 5], dtype=np.uint64)
-    keys = np.array([(1 << 32) | 2, (3 << 32) | 0, (4 << 32) | 7], dtype=np.uint64)
-    pk, off, ids = pfac.key_to_packet(keys, offsets)
-    assert pk.tolist() == [1, 3, 3]      # an empty packet never owns a start
-    assert off.tolist() == [0, 0, 1]
-    assert ids.tolist() == [2, 0, 7]
+    keys = np.array([(1 << 32) | 2, (3 << 32) | 0, (4 << 32) | 7, 0 | 9], dtype=np.uint64)
+    pk, off, ids = pfac.pfac_key_to_packet(keys, offsets)
+    assert pk.tolist() == [1, 3, 3, 0]      # an empty packet never owns a start
+    assert off.tolist() == [0, 0, 1, 0]
+    assert ids.tolist() == [2, 0, 7, 9]
+    # against a plain search over random batches
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        sizes = rng.integers(0, 9, size=int(rng.integers(1, 30)))
+        offs = np.zeros(len(sizes) + 1, np.uint64)
+        offs[1:] = np.cumsum(sizes)
+        if offs[-1] == 0:
+            continue
+        starts = rng.integers(0, int(offs[-1]), size=50)
+        ids_in = rng.integers(0, 1 << 32, size=50)
+        k = (starts.astype(np.uint64) << np.uint64(32)) | ids_in.astype(np.uint64)
+        pk, off, ids = pfac.pfac_key_to_packet(k, offs)
+        for i, s in enumerate(starts):
+            p = max(j for j in range(len(sizes)) if offs[j] <= s < offs[j + 1])
+            assert (pk[i], off[i], ids[i]) == (p, s - offs[p], ids_in[i])
+    # a start past the last packet's end, or NULL arrays, are refused
+    with pytest.raises(pfac.PfacError) as e:
+        pfac.pfac_key_to_packet(np.array([5 << 32], np.uint64), offsets)
+    assert e.value.code == pfac.PFAC_EINVAL
+    assert pfac.lib().pfac_key_to_packet(None, 1, None, 0, None, None, None) == pfac.PFAC_EINVAL
+    assert pfac.lib().pfac_key_to_packet(None, 0, None, 0, None, None, None) == pfac.PFAC_OK
+
+
+# --------------------------------------------------------------------------- save / load
+def _same_automaton(a, b):
+    ia, ib = pfac.pfac_table_info(a), pfac.pfac_table_info(b)
+    assert ia == ib
+    ta, tb = pfac.pfac_export_paper_table(a), pfac.pfac_export_paper_table(b)
+    assert np.array_equal(ta[0], tb[0]) and np.array_equal(ta[1], tb[1])
+    oa, ob = pfac.pfac_export_outputs(a), pfac.pfac_export_outputs(b)
+    assert np.array_equal(oa[0], ob[0]) and np.array_equal(oa[1], ob[1])
+    assert pfac.pfac_get_tuning(a) == pfac.pfac_get_tuning(b)
+    assert pfac.pfac_save(a) == pfac.pfac_save(b)
+
+
+def _pattern_sets():
+    rng = np.random.default_rng(31)
+    yield [], 256
+    yield [b"AB", b"AD", b"Z"], 256
+    yield [b"ab", b"abc", b"bc", b"c", b"ab"], 256           # duplicates, prefixes
+    yield [bytes(rng.integers(0, 4, size=int(rng.integers(1, 12))).astype(np.uint8))
+           for _ in range(300)], 4
+    yield [bytes(rng.integers(0, 52, size=int(rng.integers(1, 9))).astype(np.uint8))
+           for _ in range(200)], 52
+    w = W.printable_256(text_bytes=1 << 12, n_patterns=2000)
+    yield w.patterns, 256
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_save_load_round_trip(k):
+    pats, alphabet = list(_pattern_sets())[k]
+    a = pfac.pfac_build(pats, alphabet)
+    blob = pfac.pfac_save(a)
+    b = pfac.pfac_load(blob)
+    _same_automaton(a, b)
+    # a second automaton built from the same patterns is the same too
+    _same_automaton(pfac.pfac_build(pats, alphabet), b)
+
+
+def test_save_keeps_tuning():
+    pats = [b"abcd", b"abce", b"xyzw", b"qq12"]
+    a = pfac.pfac_build(pats, 256)
+    pfac.pfac_set_tuning(a, algo="tiled", grid=300, span_log2=13, root_depth=1, filter_k=3)
+    b = pfac.pfac_load(pfac.pfac_save(a))
+    assert pfac.pfac_get_tuning(b) == pfac.pfac_get_tuning(a)
+    assert pfac.pfac_table_info(b)["root_depth"] == 1 and pfac.pfac_table_info(b)["filter_k"] == 3
+
+
+def test_save_capacity_and_arguments():
+    a = pfac.pfac_build([b"ab"], 256)
+    L = pfac.lib()
+    size = C.c_uint64(0)
+    assert L.pfac_save(a.handle, None, 0, C.byref(size)) == pfac.PFAC_ECAPACITY and size.value > 64
+    small = (C.c_uint8 * 8)()
+    assert L.pfac_save(a.handle, small, 8, C.byref(size)) == pfac.PFAC_ECAPACITY
+    assert L.pfac_save(None, None, 0, C.byref(size)) == pfac.PFAC_EINVAL
+    assert L.pfac_save(a.handle, None, 0, None) == pfac.PFAC_EINVAL
+    h = C.c_void_p()
+    assert L.pfac_load(None, 0, C.byref(h)) == pfac.PFAC_EINVAL
+    assert L.pfac_load(small, 8, None) == pfac.PFAC_EINVAL
+
+
+def _fnv1a(data: bytes) -> int:
+    h = 0xcbf29ce484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _reseal(blob: bytearray) -> bytes:
+    """Recompute the header checksum (64-bit FNV-1a over bytes 0..55 and the payload)."""
+    blob[56:64] = _fnv1a(bytes(blob[:56]) + bytes(blob[64:])).to_bytes(8, "little")
+    return bytes(blob)
+
+
+def _expect_format_error(blob):
+    with pytest.raises(pfac.PfacError) as e:
+        pfac.pfac_load(blob)
+    assert e.value.code == pfac.PFAC_EFORMAT
+
+
+def test_load_rejects_truncated_and_flipped_blobs():
+    pats = [b"he", b"she", b"his", b"hers", b"h"]
+    blob = pfac.pfac_save(pfac.pfac_build(pats, 256))
+    assert _reseal(bytearray(blob)) == blob  # the test's checksum is the library's
+    for n in range(len(blob)):
+        _expect_format_error(blob[:n])
+    _expect_format_error(blob + b"\0" * 8)
+    rng = np.random.default_rng(8)
+    for pos in list(range(64)) + rng.integers(64, len(blob), size=200).tolist():
+        for bit in (0, 5):
+            bad = bytearray(blob)
+            bad[pos] ^= 1 << bit
+            _expect_format_error(bytes(bad))
+
+
+def test_load_rejects_inconsistent_tables_with_valid_checksum():
+    """Blobs whose checksum is right but whose table is not the trie of its patterns."""
+    pats = [b"ab", b"ad", b"z"]
+    a = pfac.pfac_build(pats, 256)
+    blob = bytearray(pfac.pfac_save(a))
+    Q, N = 5, 3
+    off_pat = 64
+    off_bytes = off_pat + (N + 1) * 8
+    off_first = off_bytes + 8                     # 5 pattern bytes padded to 8
+    off_bm = off_first + 24                       # 5 u32 padded to 24
+    off_of = off_bm + Q * 4 * 8
+    off_ids = off_of + 24
+    assert len(blob) == off_ids + 16
+    assert blob[off_bytes:off_bytes + 5] == b"abadz"
+
+    def mutate(at, value, size=4):
+        bad = bytearray(blob)
+        bad[at:at + size] = value.to_bytes(size, "little")
+        return _reseal(bad)
+
+    assert pfac.pfac_load(_reseal(bytearray(blob))) is not None
+    _expect_format_error(mutate(off_first + 4 * 1, 4))      # node 1's first child off by one
+    _expect_format_error(mutate(off_first + 4 * 1, 99))     # past the table
+    _expect_format_error(mutate(off_ids, 7))                # id out of range
+    _expect_format_error(mutate(off_ids, 0))                # id 0 twice (ids are 2, 0, 1)
+    _expect_format_error(mutate(off_of + 4 * 5, 2))         # a leaf that ends no pattern
+    _expect_format_error(mutate(off_bytes + 1, ord("c"), 1))  # 'ac' is not in the trie
+    _expect_format_error(mutate(16, 100))                   # alphabet below 'z'
+    _expect_format_error(mutate(off_bm + 8 * 3, 1 << 32, 8))  # an extra child bit
+    _expect_format_error(mutate(28, 9))                     # wrong longest pattern
+    _expect_format_error(mutate(40, 3 << 16))               # root depth 3 > shortest pattern
+    _expect_format_error(mutate(40, 9))                     # no such algorithm
 
 
 def test_batch_and_graph_argument_errors():

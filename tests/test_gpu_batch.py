@@ -87,7 +87,7 @@ def test_batch_edge_cases():
     assert np.array_equal(got, want)
     assert [(int(k >> np.uint64(32)), int(k & np.uint64(0xFFFFFFFF))) for k in got] == \
         [(1, 2), (3, 0), (3, 3), (4, 2)]
-    pk, off, ids = pfac.key_to_packet(got, [0, 1, 3, 3, 5])
+    pk, off, ids = pfac.pfac_key_to_packet(got, np.array([0, 1, 3, 3, 5], np.uint64))
     assert pk.tolist() == [1, 3, 3, 3] and off.tolist() == [0, 0, 0, 1] and ids.tolist() == [2, 0, 3, 2]
 
 

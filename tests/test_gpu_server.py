@@ -115,3 +115,51 @@ def test_empty_packets_and_empty_request(served):
     assert np.array_equal(got[t1]["keys"], want) and len(want) >= 2
     assert got[t2]["status"] == 0 and got[t2]["n_matches"] == 0
     srv.close()
+
+
+@pytest.fixture(scope="module")
+def served_full():
+    """The serving workload's own pattern set: 50,000 patterns of 4-256 random bytes
+    (the patterns are drawn before the payload pool, so a 64 MiB pool leaves them as in
+    the full 1 GiB stream), 300 requests of 32 packets, one planted pattern in a quarter
+    of the packets."""
+    w = W.serving_256(pool_bytes=1 << 26, max_requests=300, plant_every=4, contiguous=True)
+    assert len(w.patterns) == 50000 and w.max_len > 128
+    ac = native.AhoCorasick(w.patterns, w.alphabet)
+    want = [ac.scan_packets(r.data, r.offsets) for r in w.requests]
+    return w, want
+
+
+def test_full_pattern_set_alone_in_mix_and_batch(served_full):
+    w, want = served_full
+    print("serving_256 full pattern set: %d requests, %d keys expected"
+          % (len(w.requests), sum(len(x) for x in want)), flush=True)
+    assert sum(len(x) for x in want) > 500
+    a = pfac.pfac_build(w.patterns, w.alphabet)
+    info = pfac.pfac_table_info(a)
+    assert info["n_patterns"] == 50000 and info["max_len"] == w.max_len
+    srv = pfac.pfac_server_create(a, slots=4, max_batch_bytes=4 << 20)
+    probes = [0, 11, 150, 299]
+    alone = {}
+    for p in probes:
+        t = srv.submit(w.requests[p].data, w.requests[p].offsets)
+        alone[p] = drain(srv, [t])[t]
+        assert alone[p]["status"] == 0
+        assert np.array_equal(alone[p]["keys"], want[p]), p
+    tickets = [srv.submit(r.data, r.offsets) for r in w.requests]
+    got = drain(srv, tickets)
+    for i, t in enumerate(tickets):
+        assert got[t]["status"] == 0
+        assert np.array_equal(got[t]["keys"], want[i]), i
+    for p in probes:
+        assert np.array_equal(got[tickets[p]]["keys"], alone[p]["keys"])
+    srv.close()
+    # the same requests as one packet batch through pfac_scan_batch
+    data = np.concatenate([r.data for r in w.requests])
+    base = np.cumsum([0] + [len(r.data) for r in w.requests])
+    offs = np.concatenate([r.offsets[:-1] + np.uint64(b) for r, b in zip(w.requests, base[:-1])]
+                          + [np.array([base[-1]], dtype=np.uint64)])
+    keys = pfac.keys_to_numpy(pfac.pfac_scan_batch(
+        a, torch.from_numpy(data).cuda(), torch.from_numpy(offs.view(np.int64)).cuda()))
+    expect = np.concatenate([k + np.uint64(int(b) << 32) for k, b in zip(want, base[:-1])])
+    assert np.array_equal(keys, expect)
