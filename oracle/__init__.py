@@ -17,6 +17,9 @@ Contents
                   breadth-first node numbering of the sorted patterns, one first-child
                   offset and one alphabet-wide child bitmap per node; plus a walker that
                   applies Eq. 1 to that array, and the byte accounting of the model.
+* ``reduce``   -- the trie compression of Section 3.2 as a node count (merging nodes of
+                  the bottom levels whose suffixes agree; Eq. 2; Eqs. 3-4 read as an
+                  occupancy law).
 
 Parity status: every function here is pinned by tests under ``tests/`` against hand
 derived answers, printed values of the paper, closed forms and cross-algorithm checks.

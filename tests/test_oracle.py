@@ -339,3 +339,121 @@ def test_packet_pins_catch_planted_mistakes():
         return sorted(out)
 
     assert any(literal_no_shift(p, d, o) != e for _, _, p, d, o, e in cases)
+
+
+# ------------------------------------------------------------- compression (Section 3.2)
+from oracle import reduce  # noqa: E402
+
+
+def _reduction_cases():
+    g = _load("reduction_3_2.json")
+    return [(c["name"], [bytes.fromhex(p) for p in c["patterns"]], c["trie_nodes"],
+             {int(k): v for k, v in c["by_levels"].items()}) for c in g["cases"]]
+
+
+@pytest.mark.parametrize("case", _reduction_cases(), ids=lambda c: c[0])
+def test_reduction_hand_cases(case):
+    name, pats, q, by_levels = case
+    assert len(trie.canonical_nodes(pats)) == q
+    for levels, want in by_levels.items():
+        assert reduce.reduced_node_count(pats, levels) == want, levels
+
+
+def _moore_minimal_states(patterns, alphabet):
+    """States of the minimal DFA of the finite pattern language, by Moore's partition
+    refinement on the trie automaton completed with a dead state (a textbook algorithm
+    that shares nothing with the suffix-language count). The dead state is excluded."""
+    nodes = trie.canonical_nodes(patterns)
+    index = {s: i for i, s in enumerate(nodes)}
+    dead = len(nodes)
+    pset = {bytes(p) for p in patterns}
+    syms = sorted({c for p in patterns for c in p})
+    delta = [[index.get(s + bytes([c]), dead) for c in syms] for s in nodes] + [[dead] * len(syms)]
+    cls = [1 if s in pset else 0 for s in nodes] + [0]
+    while True:
+        sig = [(cls[q],) + tuple(cls[t] for t in delta[q]) for q in range(len(delta))]
+        ids = {}
+        new = [ids.setdefault(x, len(ids)) for x in sig]
+        if len(ids) == len(set(cls)):
+            break
+        cls = new
+    return len(set(cls)) - 1
+
+
+def test_full_reduction_is_the_minimal_automaton():
+    rng = np.random.default_rng(13)
+    for _ in range(60):
+        sigma = int(rng.choice([2, 3, 4, 26]))
+        pats = [bytes(rng.integers(0, sigma, size=int(rng.integers(1, 9))).astype(np.uint8))
+                for _ in range(int(rng.integers(1, 40)))]
+        assert reduce.reduced_node_count(pats, 64) == _moore_minimal_states(pats, sigma)
+
+
+def test_reduction_step_1_is_eq_2():
+    """levels = 1 merges only the final nodes: on prefix-free sets without duplicates
+    this is Eq. 2, Q - (|P| - 1)."""
+    rng = np.random.default_rng(17)
+    for _ in range(20):
+        sigma = int(rng.choice([2, 4, 52]))
+        m = int(rng.integers(2, 10))
+        pats = sorted({bytes(rng.integers(0, sigma, size=m).astype(np.uint8))
+                       for _ in range(int(rng.integers(1, 200)))})
+        q = len(trie.canonical_nodes(pats))
+        assert reduce.reduced_node_count(pats, 1) == trie.global_final_nodes(q, len(pats))
+
+
+def test_reduction_is_monotone_and_bounded():
+    rng = np.random.default_rng(19)
+    pats = [bytes(rng.integers(0, 4, size=int(rng.integers(3, 12))).astype(np.uint8)) for _ in range(300)]
+    q = len(trie.canonical_nodes(pats))
+    counts = [reduce.reduced_node_count(pats, k) for k in range(0, 14)]
+    assert counts[0] == q                       # nothing merged
+    assert all(a >= b for a, b in zip(counts, counts[1:]))
+    assert counts[-1] == _moore_minimal_states(pats, 4)
+
+
+def test_eq_4_occupancy_law():
+    """P(g = i) from adding patterns one at a time equals the closed occupancy form
+    C(r, i) i! S(n, i) / r^n (S: Stirling numbers of the second kind, from scipy), sums
+    to 1, and its mean is r (1 - (1 - 1/r)^n)."""
+    from math import comb, factorial
+    from fractions import Fraction
+    from scipy.special import stirling2
+    for n, r in [(1, 16), (5, 16), (12, 16), (30, 16), (20, 2704), (40, 9)]:
+        p = reduce.distinct_chain_distribution(n, r)
+        assert sum(p) == 1
+        for i in range(n + 1):
+            closed = Fraction(comb(r, i) * factorial(i) * int(stirling2(n, i, exact=True)), r ** n)
+            assert p[i] == closed, (n, r, i)
+        mean = sum(i * pi for i, pi in enumerate(p))
+        assert mean == r * (1 - (1 - Fraction(1, r)) ** n)
+    assert reduce.chains(4) == 16 and reduce.chains(52) == 2704
+
+
+def test_eq_4_against_monte_carlo():
+    """Two-symbol suffixes of random equal-length patterns: the mean number of distinct
+    ones over many draws approaches E[g] (and 2 E[g] is Eq. 4's node estimate)."""
+    rng = np.random.default_rng(23)
+    for sigma, n in [(4, 10), (4, 40), (8, 100)]:
+        trials = 3000
+        tails = rng.integers(0, sigma, size=(trials, n, 2))
+        g = np.array([len({(int(a), int(b)) for a, b in t}) for t in tails])
+        want = float(reduce.expected_reduced_tail_nodes(n, sigma)) / 2
+        sd = g.std() / np.sqrt(trials)
+        assert abs(g.mean() - want) < 5 * sd + 1e-9, (sigma, n, g.mean(), want)
+
+
+def test_reduction_planted_mistakes_fail_pins():
+    """A count that merges by height alone (ignoring the suffixes), and one that also
+    merges nodes of height `levels`, each fail the hand cases."""
+    cases = _reduction_cases()
+
+    def by_height_only(pats, levels):
+        h = reduce.heights(pats)
+        return sum(1 for s in h if h[s] >= levels) + len({h[s] for s in h if h[s] < levels})
+
+    def off_by_one(pats, levels):
+        return reduce.reduced_node_count(pats, levels + 1)
+
+    for bad in (by_height_only, off_by_one):
+        assert any(bad(p, k) != v for _, p, _, bl in cases for k, v in bl.items()), bad.__name__
