@@ -85,6 +85,27 @@ PFAC_API int pfac_build(const uint8_t *const *pats, const uint64_t *lens, uint32
 PFAC_API int pfac_build_csr(const uint8_t *bytes, const uint64_t *offsets, uint32_t n_pats,
                    uint32_t alphabet, pfac_automaton **out);
 
+/* pfac_build_ex -- pfac_build_csr with options. merge_levels selects the table the
+ * scans walk:
+ *   0        the trie of Section 3.1 (what pfac_build makes);
+ *   L >= 1   the compressed trie of Section 3.2: nodes whose height (longest path down to
+ *            a leaf) is below L are merged when everything below them is the same (the
+ *            same suffixes complete a pattern). L = 1 merges only the final nodes into one
+ *            global final node (step 1, Eq. 2); L = 3 merges the last three levels (step
+ *            2); L = 255 merges everything mergeable. Under Eq. 1 a node's children stay
+ *            consecutive, so the table stores shared blocks of children once; the
+ *            breadth-first top levels that the LDS root image folds are never shared.
+ * Matches are the same for every L (pattern ids are recovered from the rank of the
+ * spelled string among the distinct patterns, see pfac_export_records). opt may be NULL
+ * (all options 0). Errors as pfac_build, plus PFAC_EINVAL for merge_levels > 255. */
+typedef struct {
+    uint32_t merge_levels;
+    uint32_t reserved[7];
+} pfac_build_options;
+
+PFAC_API int pfac_build_ex(const uint8_t *bytes, const uint64_t *offsets, uint32_t n_pats, uint32_t alphabet,
+                           const pfac_build_options *opt, pfac_automaton **out);
+
 /* Free the automaton and its device copies. NULL is a no-op. */
 PFAC_API void pfac_destroy(pfac_automaton *a);
 
@@ -98,11 +119,20 @@ typedef struct {
     uint32_t depth;              /* trie depth (= max_len)                              */
     uint32_t node_layout;        /* 0: 8-byte node (alphabet <= 32), 1: wide node      */
     uint64_t paper_table_bytes;  /* n_nodes * (4 + ceil(alphabet / 8)), Section 3.1    */
-    uint64_t device_table_bytes; /* node arrays + pattern-id lists as stored in HBM     */
+    uint64_t device_table_bytes; /* everything a device copy holds in HBM: node arrays,
+                                    pattern ids (and rank words), path tails, pattern
+                                    bytes, LDS image source                             */
     uint32_t root_depth;         /* levels folded into the LDS-resident root image     */
     uint32_t filter_k;           /* symbols in the LDS prefix filter key (0 = none)    */
     uint32_t filter_log2_bits;   /* log2 of the filter's bit count (0 = none)          */
     uint32_t lds_image_bytes;    /* root image + filter, copied to LDS per workgroup   */
+    uint32_t merge_levels;       /* as built (pfac_build_ex)                           */
+    uint32_t reduced_nodes;      /* nodes after the compression of Section 3.2
+                                    (= n_nodes when merge_levels is 0)                  */
+    uint32_t table_records;      /* records of the walked table (= n_nodes uncompressed) */
+    uint32_t shared_base;        /* first record of a shared block                     */
+    uint64_t reduced_paper_bytes;/* reduced_nodes * (4 + ceil(alphabet / 8))            */
+    uint64_t node_array_bytes;   /* the walked table's node words in HBM               */
 } pfac_table_info_t;
 
 PFAC_API int pfac_table_info(const pfac_automaton *a, pfac_table_info_t *out);
@@ -119,6 +149,24 @@ PFAC_API int pfac_export_paper_table(const pfac_automaton *a, uint32_t *offsets,
  * ascending. first has n_nodes + 1 entries, ids n_patterns. */
 PFAC_API int pfac_export_outputs(const pfac_automaton *a, uint32_t *first, uint64_t first_cap,
                         uint32_t *ids, uint64_t ids_cap);
+
+/* The table the scans walk, one record per entry: first[x] = first child record (0 for
+ * none), bitmaps[x * words + w] as in pfac_export_paper_table, term[x] = 1 when a pattern
+ * ends there, rank[x] = its rank word. Without compression the records are the trie's
+ * nodes and rank[x] is the number of distinct pattern strings that sort (bytewise,
+ * shorter first) before the node's prefix. With compression, records from
+ * info.shared_base on lie in shared blocks and rank[x] there counts the strings spelled
+ * below the lower siblings in x's block; a walk remembers its last record u below
+ * shared_base and adds term(q) + rank[y] for every step from q into a shared record y,
+ * so that a terminal reached has rank rank[u] + that sum (its own rank word when below
+ * shared_base). cap: entries of every array (>= table_records). */
+PFAC_API int pfac_export_records(const pfac_automaton *a, uint32_t *first, uint32_t *bitmaps, uint8_t *term,
+                                 uint32_t *rank, uint64_t cap);
+
+/* Pattern ids of each distinct pattern string by rank: ids[first[r] .. first[r+1]),
+ * ascending; first has (distinct strings + 1) entries, at most n_patterns + 1. */
+PFAC_API int pfac_export_rank_ids(const pfac_automaton *a, uint32_t *first, uint64_t first_cap, uint32_t *ids,
+                                  uint64_t ids_cap);
 
 /* ------------------------------------------------------------------- saving
  * pfac_save -- serialize the automaton into buf (host memory, cap bytes): the table of

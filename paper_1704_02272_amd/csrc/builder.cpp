@@ -207,42 +207,46 @@ void finish_automaton(pfac_automaton *a) {
     a->n_term = 0;
     for (uint32_t q = 0; q < a->n_nodes; q++)
         if (a->out_first[q + 1] > a->out_first[q]) a->n_term++;
+    build_tails(a);    // over the trie
+    build_records(a);  // the walked table; tails move onto its records
+    const uint32_t R = a->n_rec;
     a->dev_nodes.clear();
     a->dev_bm.clear();
     if (a->alphabet <= 32) {
         a->layout = LAYOUT_NARROW;
         a->nw = 0;
-        a->dev_nodes.resize(a->n_nodes);
-        for (uint32_t q = 0; q < a->n_nodes; q++) {
-            uint64_t w = a->bitmap[(size_t)q * a->nbw] & 0xffffffffull;
-            w |= (uint64_t)a->first_child[q] << 32;
-            if (a->out_first[q + 1] > a->out_first[q]) w |= kTermBit;
-            a->dev_nodes[q] = w;
+        a->dev_nodes.resize(R);
+        for (uint32_t x = 0; x < R; x++) {
+            uint64_t w = a->rec_bitmap[(size_t)x * a->nbw] & 0xffffffffull;
+            w |= (uint64_t)a->rec_first[x] << 32;
+            if (a->rec_term[x]) w |= kTermBit;
+            a->dev_nodes[x] = w;
         }
     } else {
         a->layout = LAYOUT_WIDE;
         a->nw = a->nbw <= 1 ? 1 : a->nbw <= 2 ? 2 : 4;
-        a->dev_nodes.resize(a->n_nodes);
-        a->dev_bm.assign((size_t)a->n_nodes * a->nw, 0);
-        for (uint32_t q = 0; q < a->n_nodes; q++) {
-            const uint64_t *b = &a->bitmap[(size_t)q * a->nbw];
+        a->dev_nodes.resize(R);
+        a->dev_bm.assign((size_t)R * a->nw, 0);
+        for (uint32_t x = 0; x < R; x++) {
+            const uint64_t *b = &a->rec_bitmap[(size_t)x * a->nbw];
             uint64_t r1 = 0, r2 = 0, r3 = 0;
-            for (uint32_t w = 0; w < a->nbw; w++) a->dev_bm[(size_t)q * a->nw + w] = b[w];
+            for (uint32_t w = 0; w < a->nbw; w++) a->dev_bm[(size_t)x * a->nw + w] = b[w];
             if (a->nbw > 1) r1 = popc64(b[0]);
             if (a->nbw > 2) r2 = r1 + popc64(b[1]);
             if (a->nbw > 3) r3 = r2 + popc64(b[2]);
-            uint64_t m = a->first_child[q] | (r1 << 32) | (r2 << 40) | (r3 << 48);
-            if (a->out_first[q + 1] > a->out_first[q]) m |= kTermBit;
-            a->dev_nodes[q] = m;
+            uint64_t m = a->rec_first[x] | (r1 << 32) | (r2 << 40) | (r3 << 48);
+            if (a->rec_term[x]) m |= kTermBit;
+            a->dev_nodes[x] = m;
         }
     }
-    build_tails(a);
     DevTable &t = a->shape;
     t = DevTable{};
     t.alphabet = a->alphabet;
     t.layout = a->layout;
     t.nw_log2 = a->nw == 4 ? 2 : a->nw == 2 ? 1 : 0;
-    t.n_nodes = a->n_nodes;
+    t.n_nodes = R;
+    t.merged = a->merge_levels ? 1u : 0u;
+    t.shared_base = a->shared_base;
     t.min_len = a->min_len;
     t.max_len = a->max_len;
     std::vector<const uint8_t *> P(a->n_pats);
@@ -252,9 +256,14 @@ void finish_automaton(pfac_automaton *a) {
 
 int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
                     uint32_t alphabet, pfac_automaton **out) {
+    return build_automaton_ex(pats, lens, n_pats, alphabet, 0, out);
+}
+
+int build_automaton_ex(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats, uint32_t alphabet,
+                       uint32_t merge_levels, pfac_automaton **out) {
     if (!out) return PFAC_EINVAL;
     *out = nullptr;
-    if (alphabet < 1 || alphabet > 256) return PFAC_EINVAL;
+    if (alphabet < 1 || alphabet > 256 || merge_levels > kMaxMergeLevels) return PFAC_EINVAL;
     if (n_pats > 0 && (!pats || !lens)) return PFAC_EINVAL;
     uint64_t total = 0;
     uint32_t minl = UINT32_MAX, maxl = 0;
@@ -274,6 +283,7 @@ int build_automaton(const uint8_t *const *pats, const uint64_t *lens, uint32_t n
     try {
         a->alphabet = alphabet;
         a->n_pats = n_pats;
+        a->merge_levels = merge_levels;
         a->min_len = minl;
         a->max_len = maxl;
         a->nbw = (alphabet + 63) / 64;

@@ -31,6 +31,7 @@ enum Layout : uint32_t { LAYOUT_NARROW = 0, LAYOUT_WIDE = 1 };
 constexpr uint64_t kTermBit = 1ull << 63;
 constexpr uint32_t kMaxPatternLen = 1u << 24;
 constexpr uint32_t kMaxNodes = 0x7fffffffu;
+constexpr uint32_t kMaxMergeLevels = 255;  // levels >= the deepest height merge everything
 
 // Per-workgroup LDS image (copied from HBM at kernel start), in 32-bit words:
 //   [filter: 2^filter_log2 bits]         k-gram prefix filter (optional), at offset 0
@@ -71,6 +72,12 @@ struct DevTable {
     uint32_t root_word;         // word offset of the root bitmap
     uint32_t rank_word;         // word offset of the rank table
     uint32_t short_word;        // word offset of the short bitmap (= lds_words if none)
+    // Compressed tables (Section 3.2): records from shared_base on lie in shared blocks;
+    // rk[x] is the rank word of record x (see reduce.cpp), and out_first / out_ids then
+    // hold the ids by rank of the spelled string instead of by node.
+    const uint32_t *rk;
+    uint32_t merged;            // 1: compressed table, ids found by rank
+    uint32_t shared_base;       // first record of a shared block (= n_nodes when none)
 };
 
 constexpr uint32_t kFilterMul = 0x9E3779B1u;  // multiplicative hash (golden ratio)
@@ -119,7 +126,7 @@ struct DeviceCopy {
     int device = -1;
     uint32_t cus = 256;  // compute units of the device
     void *nodes = nullptr, *bm = nullptr, *out_first = nullptr, *out_ids = nullptr,
-         *lds_image = nullptr, *tails = nullptr, *tail_bytes = nullptr;
+         *lds_image = nullptr, *tails = nullptr, *tail_bytes = nullptr, *rk = nullptr;
     DevTable view{};
     std::map<void *, Workspace *> workspaces;  // keyed by stream
     // LDS images replaced by a change of tuning. Queued scans and captured graphs may
@@ -146,6 +153,16 @@ struct pfac_automaton {
     std::vector<uint32_t> depth_start;  // first node of each depth, depth 0..max_len+1
     std::vector<uint32_t> out_first, out_ids;
     std::vector<uint32_t> pat_len;
+    // The table the scans walk (reduce.cpp): the trie itself (merge_levels 0) or its
+    // compressed form (Section 3.2, nodes of height < merge_levels merged).
+    uint32_t merge_levels = 0;
+    uint32_t reduced_nodes = 0;         // nodes after merging (the paper's measure)
+    uint32_t n_rec = 0, shared_base = 0;
+    std::vector<uint32_t> rec_first;    // first child record (0: none)
+    std::vector<uint64_t> rec_bitmap;   // n_rec * nbw
+    std::vector<uint8_t> rec_term;
+    std::vector<uint32_t> rec_rank;     // rank words
+    std::vector<uint32_t> rank_first, rank_ids;  // ids of each distinct pattern string, by rank
     // Device images.
     std::vector<uint64_t> dev_nodes, dev_bm;
     std::vector<uint32_t> lds_image;
@@ -166,4 +183,10 @@ int rebuild_lds_image(pfac_automaton *a, uint32_t D, uint32_t K);
 // Derive the device images (node words, path tails, LDS image) from the trie arrays,
 // the patterns and the requested root depth / filter key. Throws std::bad_alloc.
 void finish_automaton(pfac_automaton *a);
+// The record table (plain or compressed) and the ids by rank; remaps the path tails.
+void build_records(pfac_automaton *a);
+void build_tails(pfac_automaton *a);
+// pfac_build with the table compressed (Section 3.2) below `merge_levels` (0: plain).
+int build_automaton_ex(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats, uint32_t alphabet,
+                       uint32_t merge_levels, pfac_automaton **out);
 }  // namespace pfac

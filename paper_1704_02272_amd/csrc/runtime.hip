@@ -260,6 +260,7 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, co
     if (n > 0 && !d_text) return PFAC_EINVAL;
     if (cap > 0 && !d_keys) return PFAC_EINVAL;
     if (n >= (1ull << 32)) return PFAC_ETOO_LARGE;
+    if (a->merge_levels) return PFAC_EINVAL;  // compressed tables: no scan kernel yet
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> g(a->mu);
     DeviceCopy *c = nullptr;

@@ -10,7 +10,7 @@
 //       12     4  header bytes (64)
 //       16     4  alphabet              20  4  patterns
 //       24     4  nodes                 28  4  longest pattern
-//       32     4  shortest pattern      36  4  64-bit bitmap words per node
+//       32     4  shortest pattern      36  4  merge levels of the table (pfac_build_ex)
 //       40     4  tuning: algo | span log2 << 8 | root depth << 16 | filter key << 24
 //       44     4  tuning: grid
 //       48     8  payload bytes
@@ -20,6 +20,7 @@
 // bytes, first-child offsets (u32, nodes), bitmaps (u64, nodes x words), id offsets
 // (u32, nodes + 1), ids (u32, patterns). All little-endian.
 //
+// The table the scans walk (plain or compressed, Section 3.2) is derived again on load.
 // Loading checks sizes and the checksum, then that the arrays are the breadth-first
 // trie of the stored patterns: every first-child offset is 1 + the children of all
 // earlier nodes (0 for a node without children), every leaf ends a pattern, every id
@@ -181,7 +182,7 @@ extern "C" int pfac_save(const pfac_automaton *a, uint8_t *buf, uint64_t cap, ui
     put<uint32_t>(buf, 24, a->n_nodes);
     put<uint32_t>(buf, 28, a->max_len);
     put<uint32_t>(buf, 32, a->min_len);
-    put<uint32_t>(buf, 36, a->nbw);
+    put<uint32_t>(buf, 36, a->merge_levels);
     put<uint32_t>(buf, 40, (a->algo & 0xff) | ((a->span_log2 & 0xff) << 8) | ((a->req_depth & 0xff) << 16) |
                                ((a->req_k & 0xff) << 24));
     put<uint32_t>(buf, 44, a->grid);
@@ -212,9 +213,10 @@ extern "C" int pfac_load(const uint8_t *buf, uint64_t size, pfac_automaton **out
     if (get<uint32_t>(buf, 8) != kVersion || get<uint32_t>(buf, 12) != kHeader) return PFAC_EFORMAT;
     const uint32_t alphabet = get<uint32_t>(buf, 16), n_pats = get<uint32_t>(buf, 20),
                    n_nodes = get<uint32_t>(buf, 24), maxl = get<uint32_t>(buf, 28), minl = get<uint32_t>(buf, 32),
-                   nbw = get<uint32_t>(buf, 36), tune = get<uint32_t>(buf, 40), grid = get<uint32_t>(buf, 44);
+                   levels = get<uint32_t>(buf, 36), tune = get<uint32_t>(buf, 40), grid = get<uint32_t>(buf, 44);
     const uint64_t payload = get<uint64_t>(buf, 48);
-    if (alphabet < 1 || alphabet > 256 || nbw != (alphabet + 63) / 64) return PFAC_EFORMAT;
+    if (alphabet < 1 || alphabet > 256 || levels > pfac::kMaxMergeLevels) return PFAC_EFORMAT;
+    const uint32_t nbw = (alphabet + 63) / 64;
     if (n_nodes == 0 || n_nodes > pfac::kMaxNodes || maxl > pfac::kMaxPatternLen) return PFAC_EFORMAT;
     if (payload != size - kHeader) return PFAC_EFORMAT;
     // the pattern bytes' size comes from the last pattern offset: check the offsets'
@@ -237,6 +239,7 @@ extern "C" int pfac_load(const uint8_t *buf, uint64_t size, pfac_automaton **out
         a->max_len = maxl;
         a->min_len = minl;
         a->nbw = nbw;
+        a->merge_levels = levels;
         uint64_t at = kHeader;
         a->pat_off.resize((size_t)n_pats + 1);
         memcpy(a->pat_off.data(), buf + at, off_bytes);

@@ -48,7 +48,13 @@ class TableInfo(C.Structure):
         "depth", "node_layout")] + [
         ("paper_table_bytes", C.c_uint64), ("device_table_bytes", C.c_uint64)] + [
         (n, C.c_uint32) for n in ("root_depth", "filter_k", "filter_log2_bits",
-                                  "lds_image_bytes")]
+                                  "lds_image_bytes", "merge_levels", "reduced_nodes",
+                                  "table_records", "shared_base")] + [
+        ("reduced_paper_bytes", C.c_uint64), ("node_array_bytes", C.c_uint64)]
+
+
+class BuildOptions(C.Structure):
+    _fields_ = [("merge_levels", C.c_uint32), ("reserved", C.c_uint32 * 7)]
 
 
 class Match(C.Structure):
@@ -107,6 +113,10 @@ def lib():
             "pfac_version": (C.c_int, []),
             "pfac_build_csr": (C.c_int, [P8, P64, C.c_uint32, C.c_uint32, C.POINTER(VP)]),
             "pfac_build": (C.c_int, [C.POINTER(P8), P64, C.c_uint32, C.c_uint32, C.POINTER(VP)]),
+            "pfac_build_ex": (C.c_int, [P8, P64, C.c_uint32, C.c_uint32, C.POINTER(BuildOptions),
+                                        C.POINTER(VP)]),
+            "pfac_export_records": (C.c_int, [VP, P32, P32, P8, P32, C.c_uint64]),
+            "pfac_export_rank_ids": (C.c_int, [VP, P32, C.c_uint64, P32, C.c_uint64]),
             "pfac_destroy": (None, [VP]),
             "pfac_table_info": (C.c_int, [VP, C.POINTER(TableInfo)]),
             "pfac_export_paper_table": (C.c_int, [VP, P32, C.c_uint64, P32, C.c_uint64]),
@@ -185,18 +195,45 @@ class Automaton:
         self.close()
 
 
-def pfac_build(patterns, alphabet: int = 256) -> Automaton:
-    """Build the compressed table of ``patterns`` (a list of bytes)."""
+def pfac_build(patterns, alphabet: int = 256, merge_levels: int = 0) -> Automaton:
+    """Build the table of ``patterns`` (a list of bytes): the trie of Section 3.1, or with
+    ``merge_levels`` > 0 its compressed form of Section 3.2 (``pfac_build_ex``)."""
     offs = np.zeros(len(patterns) + 1, dtype=np.uint64)
     if patterns:
         np.cumsum([len(p) for p in patterns], out=offs[1:])
     data = np.frombuffer(b"".join(bytes(p) for p in patterns) or b"\0", dtype=np.uint8).copy()
     h = C.c_void_p()
-    rc = lib().pfac_build_csr(data.ctypes.data_as(C.POINTER(C.c_uint8)),
-                              offs.ctypes.data_as(C.POINTER(C.c_uint64)), len(patterns),
-                              alphabet, C.byref(h))
+    P8, P64 = C.POINTER(C.c_uint8), C.POINTER(C.c_uint64)
+    if merge_levels:
+        opt = BuildOptions(merge_levels)
+        rc = lib().pfac_build_ex(data.ctypes.data_as(P8), offs.ctypes.data_as(P64), len(patterns), alphabet,
+                                 C.byref(opt), C.byref(h))
+    else:
+        rc = lib().pfac_build_csr(data.ctypes.data_as(P8), offs.ctypes.data_as(P64), len(patterns),
+                                  alphabet, C.byref(h))
     _check(rc, "pfac_build")
     return Automaton(h.value, max((len(p) for p in patterns), default=0))
+
+
+def pfac_export_records(a: Automaton) -> dict:
+    """The walked table: first, bitmaps (records x ceil(alphabet/32) uint32), term, rank,
+    plus shared_base and the ids by rank (rank_first, rank_ids)."""
+    info = pfac_table_info(a)
+    n, words = info["table_records"], (info["alphabet"] + 31) // 32
+    first = np.zeros(n, np.uint32)
+    bm = np.zeros((n, words), np.uint32)
+    term = np.zeros(n, np.uint8)
+    rank = np.zeros(n, np.uint32)
+    P32 = C.POINTER(C.c_uint32)
+    _check(lib().pfac_export_records(a.handle, first.ctypes.data_as(P32), bm.ctypes.data_as(P32),
+                                     term.ctypes.data_as(C.POINTER(C.c_uint8)), rank.ctypes.data_as(P32), n),
+           "pfac_export_records")
+    rf = np.zeros(info["n_patterns"] + 1, np.uint32)
+    ri = np.zeros(max(info["n_patterns"], 1), np.uint32)
+    _check(lib().pfac_export_rank_ids(a.handle, rf.ctypes.data_as(P32), len(rf), ri.ctypes.data_as(P32), len(ri)),
+           "pfac_export_rank_ids")
+    return {"first": first, "bitmaps": bm, "term": term, "rank": rank, "shared_base": info["shared_base"],
+            "rank_first": rf, "rank_ids": ri[:info["n_patterns"]]}
 
 
 def pfac_table_info(a: Automaton) -> dict:
