@@ -40,7 +40,8 @@ WORKLOADS = {
                     "patterns (4-128 B, heads from a depth-6 branching-3 tree), alphabet 256"),
 }
 
-KERNEL_SOURCES = ["paper_1704_02272_amd/csrc/kernels_scan.hip",
+KERNEL_SOURCES = ["paper_1704_02272_amd/csrc/scan_kernels.h",
+                  "paper_1704_02272_amd/csrc/kernels_scan.hip",
                   "paper_1704_02272_amd/csrc/kernels_plain.hip",
                   "paper_1704_02272_amd/csrc/scan_internal.h",
                   "paper_1704_02272_amd/csrc/pfac_impl.h"]
@@ -348,6 +349,143 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def equal_length_patterns(alphabet: int, count: int, length: int, seed: int):
+    """``count`` distinct random patterns of ``length`` symbols over 0..alphabet-1 (the
+    synthetic pattern sets of Section 4.1)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    pats = set()
+    while len(pats) < count:
+        block = rng.integers(0, alphabet, size=(count - len(pats), length)).astype(np.uint8)
+        pats.update(row.tobytes() for row in block)
+    return sorted(pats)[:count]
+
+
+def bench_sizes(args):
+    """Trie sizes of Section 4.1 (Figs. 4 and 5): 20-symbol random patterns at
+    alphabets 4 and 52, for several pattern counts. Bitmapped trie (Section 3.1) and its
+    compressed form (Section 3.2) from the library; an array trie (one 4-byte child
+    pointer per symbol per node) and a binary trie (symbols as ceil(log2 alphabet)-bit
+    codes, two 4-byte child pointers per node) as the textbook baselines the figures
+    plot. No GPU."""
+    import math
+
+    import paper_1704_02272_amd.pfac as pfac
+    rows = []
+    for alphabet in (4, 52):
+        bits = max(1, math.ceil(math.log2(alphabet)))
+        for count in (10, 100, 1000, 10000, 100000):
+            pats = equal_length_patterns(alphabet, count, 20, seed=alphabet * 1000 + count)
+            info = {lv: pfac.pfac_table_info(pfac.pfac_build(pats, alphabet, merge_levels=lv)) for lv in (0, 1, 3, 255)}
+            q = info[0]["n_nodes"]
+            bin_prefixes = set()
+            for p in pats:
+                code = "".join(format(c, "0%db" % bits) for c in p)
+                bin_prefixes.update(code[:i] for i in range(1, len(code) + 1))
+            row = {"alphabet": alphabet, "patterns": count, "length": 20,
+                   "array_trie_bytes": q * 4 * alphabet,
+                   "binary_trie_bytes": (1 + len(bin_prefixes)) * 8,
+                   "bitmapped_nodes": q, "bitmapped_bytes": info[0]["paper_table_bytes"]}
+            for lv in (1, 3, 255):
+                row["reduced%d_nodes" % lv] = info[lv]["reduced_nodes"]
+                row["reduced%d_bytes" % lv] = info[lv]["reduced_paper_bytes"]
+                row["reduced%d_saving" % lv] = round(1 - info[lv]["reduced_nodes"] / q, 4)
+                row["device%d_records" % lv] = info[lv]["table_records"]
+            row["device0_table_bytes"] = info[0]["device_table_bytes"]
+            row["device3_table_bytes"] = info[3]["device_table_bytes"]
+            rows.append(row)
+    for alphabet in (4, 52):
+        sel = [r for r in rows if r["alphabet"] == alphabet]
+        for lv in (1, 3, 255):
+            rows.append({"alphabet": alphabet, "mean_saving_levels_%d" % lv:
+                         round(sum(r["reduced%d_saving" % lv] for r in sel) / len(sel), 4)})
+    print(json.dumps({"mode": "sizes", "rows": rows}), flush=True)
+
+
+def bench_sweep(args):
+    """Throughput over alphabets and pattern counts (Section 4.3, Figs. 7-9 shape): for
+    every alphabet in 4, 8, ..., 52 and 256 and every count in 1, 10, 100, 1,000 of
+    20-symbol random patterns, scan five seeded 100 MiB texts of uniform symbols
+    (Section 4: five synthetic files, 100 runs each, the mean reported) with the plain
+    and the compressed (three merged levels) table. Each configuration is first checked
+    against the oracle on a 4 MiB slice. Also the oracle itself (all host threads) at
+    alphabet 52 with 100 patterns on 100 and 200 MiB texts (Fig. 9)."""
+    import numpy as np
+    import torch
+
+    import paper_1704_02272_amd.pfac as pfac
+    from oracle import native
+
+    dev = torch.device("cuda:0")
+    n = args.sweep_mib << 20
+    reps = args.steps
+    alphabets = list(range(4, 53, 4)) + [256]
+    counts = [1, 10, 100, 1000]
+    stream = torch.cuda.current_stream()
+    import ctypes
+    scan_async = pfac.lib().pfac_scan_async
+    rows = []
+    for alphabet in alphabets:
+        texts = []
+        for f in range(args.sweep_files):
+            rng = np.random.default_rng(10_000 + alphabet * 10 + f)
+            texts.append(torch.from_numpy(rng.integers(0, alphabet, size=n, dtype=np.uint8)).to(dev))
+        for count in counts:
+            pats = equal_length_patterns(alphabet, count, 20, seed=alphabet * 7919 + count)
+            row = {"alphabet": alphabet, "patterns": count}
+            for levels in (0, 3):
+                a = pfac.pfac_build(pats, alphabet, merge_levels=levels)
+                sl = texts[0][: 4 << 20]
+                got = pfac.keys_to_numpy(pfac.pfac_scan(a, sl))
+                want = native.AhoCorasick(pats, alphabet).scan(sl.cpu().numpy())
+                if not np.array_equal(got, want):
+                    raise RuntimeError("sweep parity failed at alphabet %d, %d patterns, levels %d"
+                                       % (alphabet, count, levels))
+                keys = torch.empty(max(1 << 16, int(len(want)) * 64), dtype=torch.int64, device=dev)
+                cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+                per_file = []
+                for t in texts:
+                    call = (a.handle, ctypes.c_void_p(t.data_ptr()), t.numel(), ctypes.c_void_p(keys.data_ptr()),
+                            keys.numel(), ctypes.c_void_p(cnt.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+                    for _ in range(2):
+                        scan_async(*call)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    bad = 0
+                    for _ in range(reps):
+                        bad |= scan_async(*call)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    if bad:
+                        raise RuntimeError("pfac_scan_async failed in the sweep")
+                    if int(cnt.item()) > keys.numel():
+                        raise RuntimeError("sweep key buffer too small")
+                    per_file.append(e0.elapsed_time(e1) / reps)
+                ms = float(np.mean(per_file))
+                tag = "plain" if levels == 0 else "reduced3"
+                row[tag + "_gbit_s"] = round(8.0 * n / (ms / 1e3) / 1e9, 1)
+                row[tag + "_ms"] = round(ms, 4)
+                row[tag + "_hbm_frac"] = round(n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+            row["matches_4mib_slice"] = int(len(want))
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+        del texts
+    # Fig. 9: the oracle on the host at alphabet 52, 100 patterns, 100 and 200 MiB
+    cpu = []
+    if not args.no_cpu:
+        pats = equal_length_patterns(52, 100, 20, seed=52 * 7919 + 100)
+        ac = native.AhoCorasick(pats, 52)
+        for mib in (100, 200):
+            t = np.random.default_rng(52).integers(0, 52, size=mib << 20, dtype=np.uint8)
+            t0 = time.perf_counter()
+            ac.scan(t, threads=native.threads())
+            el = time.perf_counter() - t0
+            cpu.append({"mib": mib, "gbit_s": round(8.0 * (mib << 20) / el / 1e9, 3), "threads": native.threads()})
+    print(json.dumps({"mode": "sweep", "text_mib": args.sweep_mib, "files": args.sweep_files, "reps": reps,
+                      "pattern_length": 20, "rows": rows, "cpu_oracle_alphabet52_100pats": cpu,
+                      "cpu_model": cpu_model()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,18 +503,24 @@ def main():
     ap.add_argument("--plant-every", type=int, default=0, help="serving: planted variant")
     ap.add_argument("--verify", type=int, default=256,
                     help="serving: requests (evenly spread) whose keys are checked against the oracle")
+    ap.add_argument("--sweep-mib", type=int, default=100, help="sweep: MiB per text")
+    ap.add_argument("--sweep-files", type=int, default=5, help="sweep: seeded texts per alphabet")
     ap.add_argument("--baseline-steps", type=int, default=3,
                     help="packets: timed passes of the per-packet baseline")
-    ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host"],
+    ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host", "sizes", "sweep"],
                     help="copy: a plain device-to-device copy of the workload's text, the "
                          "reference that scales the HBM byte counters of the scan; host: the "
                          "text starts in host memory (pinned, then pageable) and crosses PCIe "
-                         "inside the timed region")
+                         "inside the timed region; sizes: the trie-size study of Section 4.1 (no GPU); "
+                         "sweep: throughput over alphabets and pattern counts (Section 4.3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "sizes":
+        bench_sizes(args)
+        return
 
     import numpy as np
     import torch
@@ -385,6 +529,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "sweep":
+        bench_sweep(args)
+        return
     if args.workload == "serving_256":
         bench_serving(args)
         return

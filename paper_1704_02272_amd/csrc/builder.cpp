@@ -182,6 +182,13 @@ void build_tails(pfac_automaton *a) {
     }
 }
 
+}  // namespace pfac
+
+// Device copies are freed by the runtime (release_device_copies).
+pfac_automaton::~pfac_automaton() { pfac::release_device_copies(this); }
+
+namespace pfac {
+
 int rebuild_lds_image(pfac_automaton *a, uint32_t D, uint32_t K) {
     if (!a || a->n_pats == 0) return (D || K) ? PFAC_EINVAL : PFAC_OK;
     const bool pack2 = a->alphabet <= 4;

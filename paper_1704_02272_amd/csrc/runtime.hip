@@ -97,6 +97,7 @@ void free_copy(DeviceCopy *c) {
     hipFree(c->lds_image);
     hipFree(c->tails);
     hipFree(c->tail_bytes);
+    hipFree(c->rk);
     for (void *p : c->retired) hipFree(p);
     hipSetDevice(prev);
     delete c;
@@ -133,8 +134,11 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
         c->cus = (uint32_t)cus;
     rc = upload_vec(a->dev_nodes, &c->nodes);
     if (!rc && a->layout == LAYOUT_WIDE) rc = upload_vec(a->dev_bm, &c->bm);
-    if (!rc) rc = upload_vec(a->out_first, &c->out_first);
-    if (!rc) rc = upload_vec(a->out_ids, &c->out_ids);
+    // ids by node (plain trie), or by rank of the spelled string plus the rank words
+    // (compressed trie)
+    if (!rc) rc = upload_vec(a->merge_levels ? a->rank_first : a->out_first, &c->out_first);
+    if (!rc) rc = upload_vec(a->merge_levels ? a->rank_ids : a->out_ids, &c->out_ids);
+    if (!rc && a->merge_levels) rc = upload_vec(a->rec_rank, &c->rk);
     if (!rc) rc = upload_vec(a->lds_image, &c->lds_image);
     if (!rc) rc = upload_vec(a->dev_tails, &c->tails);
     if (!rc) rc = upload_vec(a->pat_bytes, &c->tail_bytes);
@@ -150,6 +154,7 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     c->view.lds_image = (const uint32_t *)c->lds_image;
     c->view.tails = (const uint32_t *)c->tails;
     c->view.tail_bytes = (const uint8_t *)c->tail_bytes;
+    c->view.rk = (const uint32_t *)c->rk;
     a->copies.push_back(c);
     *out = c;
     return PFAC_OK;
@@ -195,7 +200,6 @@ static int get_workspace(DeviceCopy *c, void *stream, uint64_t n, uint32_t algo,
 
 using namespace pfac;
 
-pfac_automaton::~pfac_automaton() { release_device_copies(this); }
 
 extern "C" int pfac_upload(pfac_automaton *a, int device) {
     if (!a) return PFAC_EINVAL;
@@ -260,7 +264,6 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, co
     if (n > 0 && !d_text) return PFAC_EINVAL;
     if (cap > 0 && !d_keys) return PFAC_EINVAL;
     if (n >= (1ull << 32)) return PFAC_ETOO_LARGE;
-    if (a->merge_levels) return PFAC_EINVAL;  // compressed tables: no scan kernel yet
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> g(a->mu);
     DeviceCopy *c = nullptr;
@@ -447,6 +450,7 @@ static int reupload_lds_images(pfac_automaton *a) {
         v.out_ids = c->view.out_ids;
         v.tails = c->view.tails;
         v.tail_bytes = c->view.tail_bytes;
+        v.rk = c->view.rk;
         v.lds_image = (const uint32_t *)c->lds_image;
         c->view = v;
     }
@@ -456,6 +460,7 @@ static int reupload_lds_images(pfac_automaton *a) {
 
 static int set_tuning_locked(pfac_automaton *a, const pfac_tuning *t) {
     if (t->algo > PFAC_ALGO_TILED) return PFAC_EINVAL;
+    if (t->algo == PFAC_ALGO_PLAIN && a->merge_levels) return PFAC_EINVAL;  // the baseline walks the plain trie
     const uint32_t span = t->span_log2;  // 0: chosen per scan from the text size
     if (span && (span < kMinSpanLog2 || span > kMaxSpanLog2)) return PFAC_EINVAL;
     if (t->root_depth != a->req_depth || t->filter_k != a->req_k) {

@@ -125,7 +125,7 @@ struct SpanOut {
     uint32_t *nh;
     uint32_t *ovf;
     uint64_t *rec;
-    uint32_t rec_log2;  // log2 of the records per span (set per launch)
+    uint32_t rec_log2;  // log2 of the records per span (0: rec_cap_log2 of the span, set per launch)
 };
 
 // Span length chosen when the tuning leaves it open: the longest power of two (4 to
@@ -173,5 +173,10 @@ constexpr uint64_t kCountOverflow = ~0ull - 1;
 int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                  uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
                  const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s);
+// The same for a compressed table (t.merged; launch_tiled dispatches to it).
+int launch_tiled_merged(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets,
+                        uint32_t n_packets, uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so,
+                        const TileState &ts, const uint64_t *sizes, uint32_t grid, uint32_t span_log2,
+                        hipStream_t s);
 
 }  // namespace pfac

@@ -77,6 +77,12 @@ def test_reduced_counts_and_walk(case, levels):
     off, bm = pfac.pfac_export_paper_table(a)
     want_off, _ = trie.paper_layout(pats, alphabet)
     assert off.tolist() == want_off
+    # the levels the LDS root image folds keep their breadth-first indices and bitmaps
+    rec = pfac.pfac_export_records(a)
+    d0 = min(min(len(p) for p in pats), 8 if alphabet <= 4 else 2)
+    top = sum(1 for s in trie.canonical_nodes(pats) if len(s) <= d0)
+    assert rec["shared_base"] >= top
+    assert np.array_equal(rec["bitmaps"][:top], bm[:top])
     rng = np.random.default_rng(len(pats) + levels)
     hi = alphabet + (1 if alphabet < 256 else 0)
     text = bytes(rng.integers(0, hi, size=600).astype(np.uint8))
