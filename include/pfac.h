@@ -133,6 +133,9 @@ typedef struct {
     uint32_t shared_base;        /* first record of a shared block                     */
     uint64_t reduced_paper_bytes;/* reduced_nodes * (4 + ceil(alphabet / 8))            */
     uint64_t node_array_bytes;   /* the walked table's node words in HBM               */
+    uint64_t stream_scratch;     /* per-stream scratch areas held on all devices (one
+                                    per stream a scan ran on; freed with the automaton,
+                                    or when the library's own streams are destroyed)    */
 } pfac_table_info_t;
 
 PFAC_API int pfac_table_info(const pfac_automaton *a, pfac_table_info_t *out);

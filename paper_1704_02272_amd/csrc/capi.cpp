@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "pfac.h"
+#include "kernels.h"
 #include "pfac_impl.h"
 
 using namespace pfac;
@@ -113,6 +114,7 @@ extern "C" int pfac_table_info(const pfac_automaton *a, pfac_table_info_t *o) {
     o->shared_base = a->shared_base;
     o->reduced_paper_bytes = (uint64_t)a->reduced_nodes * node_bytes;
     o->node_array_bytes = a->dev_nodes.size() * 8 + a->dev_bm.size() * 8;
+    o->stream_scratch = pfac::workspace_count(const_cast<pfac_automaton *>(a));
     return PFAC_OK;
 }
 

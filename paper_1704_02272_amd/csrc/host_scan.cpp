@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "pfac.h"
+#include "kernels.h"
 #include "pfac_impl.h"
 
 namespace {
@@ -42,6 +43,7 @@ struct Pipeline {
     ~Pipeline() {
         for (Slot &s : slot) {
             if (s.s) (void)hipStreamSynchronize(s.s);
+            if (s.s) pfac::release_stream(a, s.s);  // scratch keyed by this stream
             hipHostFree(s.h_stage);
             hipFree(s.d_text);
             hipFree(s.d_keys);

@@ -17,4 +17,11 @@ uint64_t plain_blocks(uint64_t n);
 // Store one value to device memory (graph-capture safe: a kernel, not a memset).
 int launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t s);
 
+// Free the scratch the automaton keeps for `stream` on every device (after the stream
+// has drained). Owners of streams they destroy call it first, so scratch keyed by a
+// stream's address never outlives the stream.
+void release_stream(pfac_automaton *a, void *stream);
+// Number of per-stream scratch areas the automaton holds (all devices).
+size_t workspace_count(pfac_automaton *a);
+
 }  // namespace pfac

@@ -110,6 +110,30 @@ int launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+void release_stream(pfac_automaton *a, void *stream) {
+    if (!a) return;
+    std::lock_guard<std::mutex> g(a->mu);
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    for (DeviceCopy *c : a->copies) {
+        auto it = c->workspaces.find(stream);
+        if (it == c->workspaces.end()) continue;
+        (void)hipSetDevice(c->device);
+        if (stream) (void)hipStreamSynchronize((hipStream_t)stream);
+        free_workspace(it->second);
+        c->workspaces.erase(it);
+    }
+    (void)hipSetDevice(prev);
+}
+
+size_t workspace_count(pfac_automaton *a) {
+    if (!a) return 0;
+    std::lock_guard<std::mutex> g(a->mu);
+    size_t k = 0;
+    for (DeviceCopy *c : a->copies) k += c->workspaces.size();
+    return k;
+}
+
 void release_device_copies(pfac_automaton *a) {
     for (DeviceCopy *c : a->copies) free_copy(c);
     a->copies.clear();

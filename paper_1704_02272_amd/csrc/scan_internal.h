@@ -160,6 +160,20 @@ struct TileState {
     uint32_t *ctrl;
 };
 
+// End of the packet holding global position s of a packet batch (offsets: n_packets + 1
+// ascending byte offsets), by binary search. A position at or past offsets[n_packets]
+// (offsets that end before the batch's bytes do) gets offsets[n_packets]: every read
+// stays inside the array, and a walk from there stops at once.
+__host__ __device__ inline uint64_t packet_end(const uint64_t *__restrict__ offsets, uint32_t n_packets, uint64_t s) {
+    uint32_t lo = 0, hi = n_packets;  // first i with offsets[i+1] > s
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (offsets[mid + 1] > s) hi = mid;
+        else lo = mid + 1;
+    }
+    return offsets[lo < n_packets ? lo + 1 : n_packets];
+}
+
 // Count value that reports a device-side error (the host maps it to a status).
 constexpr uint64_t kCountTimeout = ~0ull;
 constexpr uint64_t kCountOverflow = ~0ull - 1;

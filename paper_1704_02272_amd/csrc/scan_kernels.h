@@ -344,18 +344,6 @@ struct RootWalk {
     }
 };
 
-// End of the packet holding global position s (packet batches), by binary search.
-__device__ __forceinline__ uint64_t packet_end(const uint64_t *__restrict__ offsets,
-                                               uint32_t n_packets, uint64_t s) {
-    uint32_t lo = 0, hi = n_packets;  // first i with offsets[i+1] > s
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (offsets[mid + 1] > s) hi = mid;
-        else lo = mid + 1;
-    }
-    return offsets[lo + 1];
-}
-
 // Text stream loads through a buffer resource over the text: the per-step offset is a
 // scalar (wave-uniform) register and the lane's 16-byte slot a fixed vector offset, so a
 // load costs no vector address arithmetic. 0x20000: the raw-buffer word 3 of gfx9.

@@ -24,6 +24,7 @@
 
 #include "pfac.h"
 #include "pfac_impl.h"
+#include "kernels.h"
 #include "scan_internal.h"
 
 namespace {
@@ -86,7 +87,8 @@ struct pfac_server {
 
 namespace {
 
-void free_slot(Slot &s) {
+void free_slot(pfac_automaton *a, Slot &s) {
+    if (s.s) pfac::release_stream(a, s.s);  // overflow rescans keep scratch keyed by the stream
     if (s.g) pfac_graph_destroy(s.g);
     if (s.done) (void)hipEventDestroy(s.done);
     hipFree(s.d_bytes);
@@ -392,7 +394,7 @@ extern "C" int pfac_server_create(pfac_automaton *a, const pfac_server_config *c
         }
     }
     if (rc) {
-        for (Slot &s : sv->slots) free_slot(s);
+        for (Slot &s : sv->slots) free_slot(sv->a, s);
         delete sv;
         return rc;
     }
@@ -526,7 +528,7 @@ extern "C" void pfac_server_destroy(pfac_server *sv) {
     (void)hipSetDevice(sv->device);
     for (Slot &s : sv->slots) {
         if (s.s) (void)hipStreamSynchronize(s.s);
-        free_slot(s);
+        free_slot(sv->a, s);
     }
     (void)hipSetDevice(prev);
     for (pfac_result &r : sv->results) free(r.keys);

@@ -50,7 +50,8 @@ class TableInfo(C.Structure):
         (n, C.c_uint32) for n in ("root_depth", "filter_k", "filter_log2_bits",
                                   "lds_image_bytes", "merge_levels", "reduced_nodes",
                                   "table_records", "shared_base")] + [
-        ("reduced_paper_bytes", C.c_uint64), ("node_array_bytes", C.c_uint64)]
+        ("reduced_paper_bytes", C.c_uint64), ("node_array_bytes", C.c_uint64),
+        ("stream_scratch", C.c_uint64)]
 
 
 class BuildOptions(C.Structure):

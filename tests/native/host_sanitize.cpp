@@ -12,11 +12,13 @@
 #include <vector>
 
 #include "pfac.h"
+#include "scan_internal.h"
 
 struct pfac_automaton;
 namespace pfac {
 // The host-only automata built here never reach a device.
 void release_device_copies(pfac_automaton *) {}
+size_t workspace_count(pfac_automaton *) { return 0; }
 }  // namespace pfac
 
 static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
@@ -82,7 +84,31 @@ static std::vector<uint64_t> walk(pfac_automaton *a, uint32_t alphabet, const st
     return out;
 }
 
+// packet_end (the packet-batch walks' end) against a linear search, on offsets held in
+// an array of exactly n_packets + 1 words (the sanitizer sees any read past it), also
+// for offsets that end before the batch's bytes (positions past the last offset).
+static void check_packet_end() {
+    for (int trial = 0; trial < 200; trial++) {
+        const uint32_t np = rnd(12);
+        uint64_t *off = new uint64_t[np + 1];
+        off[0] = 0;
+        for (uint32_t i = 1; i <= np; i++) off[i] = off[i - 1] + rnd(5);  // empty packets too
+        const uint64_t n = off[np] + rnd(6);  // bytes may run past the last offset
+        for (uint64_t s = 0; s < n + 2; s++) {
+            uint64_t want = off[np];
+            for (uint32_t i = 0; i < np; i++)
+                if (off[i + 1] > s) {
+                    want = off[i + 1];
+                    break;
+                }
+            CHECK(pfac::packet_end(off, np, s) == want);
+        }
+        delete[] off;
+    }
+}
+
 int main() {
+    check_packet_end();
     const uint32_t alphabets[] = {2, 4, 26, 256};
     const uint32_t levels[] = {0, 1, 3, 255};
     for (int trial = 0; trial < 48; trial++) {

@@ -63,3 +63,19 @@ def test_tiny_and_empty_texts():
     assert len(pfac.pfac_scan_host(a, np.zeros(0, np.uint8))) == 0
     got = pfac.pfac_scan_host(a, np.frombuffer(b"xabcab", np.uint8), chunk_bytes=1)
     assert got["start"].tolist() == [1, 1, 2, 4, 5] and got["pattern_id"].tolist() == [0, 2, 1, 0, 1]
+
+
+def test_host_scans_release_their_stream_scratch():
+    # every host scan makes and destroys its own streams; the scratch the automaton keeps
+    # per stream must go with them, so repeated calls hold no more of it than one did
+    rng = np.random.default_rng(23)
+    pats = [bytes(rng.integers(0, 256, size=int(rng.integers(4, 12))).astype(np.uint8)) for _ in range(50)]
+    text = rng.integers(0, 256, size=(3 << 20) + 5).astype(np.uint8)
+    a = pfac.pfac_build(pats, 256)
+    want = native.AhoCorasick(pats, 256).scan(text)
+    _check(pfac.pfac_scan_host(a, text, chunk_bytes=1 << 20), want)
+    held = pfac.pfac_table_info(a)["stream_scratch"]
+    assert held == 0
+    for _ in range(5):
+        _check(pfac.pfac_scan_host(a, text, chunk_bytes=1 << 20), want)
+    assert pfac.pfac_table_info(a)["stream_scratch"] == held

@@ -1,10 +1,10 @@
 """GPU parity of the sampled prefilter form: byte patterns of four or more bytes with a
-4-byte filter key, where only every second start is probed (with its 3-gram) and the
-candidates are checked 64 at a time from the step staged in LDS. The edge cases of that
-path, each compared element by element with the oracle: texts shorter than a step,
+4-byte filter key, where only every second start is probed (with its 3-gram) and each
+lane then checks the 4-grams of its own candidates from its registers. The edge cases of
+that path, each compared element by element with the oracle: texts shorter than a step,
 ragged ends, several span lengths, texts that do not start on a 16-byte boundary (the
-guarded loads), matches across lane, step and span boundaries, steps with more
-candidates than one listing window, and spans with more matching starts than records."""
+guarded loads), matches across lane, step and span boundaries, lanes with many
+candidates in one step, and spans with more matching starts than records."""
 import numpy as np
 import pytest
 
