@@ -223,6 +223,26 @@ PFAC_API int pfac_upload(pfac_automaton *a, int device);
 PFAC_API int pfac_scan_async(pfac_automaton *a, const uint8_t *d_text, uint64_t n,
                              uint64_t *d_keys, uint64_t cap, uint64_t *d_count, void *stream);
 
+/* pfac_scan_noalloc -- pfac_scan_async for callers that cannot allocate memory (code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same keys and count, but the call allocates nothing. Its scratch (per
+ * span counts and match records) is one fixed array of about 8.1 MiB per device, held
+ * from the library's first use of that device until the process ends. Limits and rules:
+ *   - the automaton must already be on the current device (pfac_upload, or any earlier
+ *     scan there): PFAC_EINVAL otherwise, since the upload allocates;
+ *   - the text may take at most 4,096 spans: 256 MiB when the span length is left to
+ *     the library (it is then lengthened as needed, up to 64 KiB), 4,096 times a tuned
+ *     span length otherwise; PFAC_ETOO_LARGE beyond;
+ *   - every call on one device shares that device's array: calls that overlap in time on
+ *     one device (on different streams, or from different threads or automata) race
+ *     and give wrong results; order them on one stream or wait in between;
+ *   - a span keeps at most 256 match records (pfac_scan_async keeps up to span / 64);
+ *     a span with more matching starts is walked again during placement, still exact.
+ * d_keys, cap, d_count and stream as pfac_scan_async. Errors: PFAC_EINVAL (as
+ * pfac_scan_async, or no device copy), PFAC_ETOO_LARGE, PFAC_ENODEVICE, PFAC_EHIP. */
+PFAC_API int pfac_scan_noalloc(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
+                               uint64_t cap, uint64_t *d_count, void *stream);
+
 /* pfac_scan -- pfac_scan_async, then wait for `stream` and return the count in *h_count
  * (host memory). Returns PFAC_ECAPACITY when the count exceeds cap (*h_count = the
  * capacity needed; d_keys content unspecified). */

@@ -2,6 +2,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "pfac.h"
@@ -139,6 +140,37 @@ void release_device_copies(pfac_automaton *a) {
     a->copies.clear();
 }
 
+// Scratch of pfac_scan_noalloc: one array per device, kept until the process ends. Host
+// code never uses the array's name as an address (that is a host-side stand-in); it uses
+// the device address hipGetSymbolAddress returns, fetched once per device.
+// Layout for up to kNoAllocSpans spans with 2^kNoAllocRecLog2 records each:
+//   [records: spans << rec_log2 u64][cnt: spans u64][nh: spans u32][ovf: spans u32]
+//   [look-back words: spans / kBlockSpans u64][ctrl: 4 u32]
+constexpr uint32_t kNoAllocSpans = 4096;
+constexpr uint32_t kNoAllocRecLog2 = 8;
+constexpr uint64_t kNoAllocRecBytes = ((uint64_t)kNoAllocSpans << kNoAllocRecLog2) * 8;
+constexpr uint64_t kNoAllocBytes = kNoAllocRecBytes + (uint64_t)kNoAllocSpans * 16 +
+                                   (uint64_t)(kNoAllocSpans / kBlockSpans) * 8 + 16;
+static_assert(kNoAllocSpans <= kDirectMaxSpans, "placement without look-back: no state carried between calls");
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kNoAllocMaxDevices];  // device address of `scratch` per device, once fetched
+
+// Device address of the scratch array on device `dev` (current), fetched on first use.
+static int scratch_address(int dev, uint8_t **out) {
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return PFAC_ENODEVICE;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PFAC_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = (uint8_t *)g_scratch_ptr[dev];
+    return PFAC_OK;
+}
+
 // Device copy for the current device, uploading it on first use. Caller holds a->mu.
 static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     int dev = 0;
@@ -179,6 +211,10 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     c->view.tails = (const uint32_t *)c->tails;
     c->view.tail_bytes = (const uint8_t *)c->tail_bytes;
     c->view.rk = (const uint32_t *)c->rk;
+    // set-up of pfac_scan_noalloc on this device (its scratch array's device address);
+    // a failure here is reported by that call, which tries again
+    uint8_t *sp = nullptr;
+    (void)scratch_address(dev, &sp);
     a->copies.push_back(c);
     *out = c;
     return PFAC_OK;
@@ -359,6 +395,50 @@ extern "C" int pfac_scan_batch(pfac_automaton *a, const uint8_t *d_bytes, const 
                          : scan_enqueue(a, d_bytes, n_bytes, d_offsets, n_pkts, d_keys, cap, nullptr, stream, &w);
     if (rc) return rc;
     return finish_count(w, cap, h_count, stream);
+}
+
+// ------------------------------------------------------------------ scans that allocate nothing
+extern "C" int pfac_scan_noalloc(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint64_t *d_keys,
+                                 uint64_t cap, uint64_t *d_count, void *stream) {
+    if (!a || !d_count || (n > 0 && !d_text) || (cap > 0 && !d_keys)) return PFAC_EINVAL;
+    if (n >= (1ull << 32)) return PFAC_ETOO_LARGE;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PFAC_ENODEVICE;
+    std::lock_guard<std::mutex> g(a->mu);
+    DeviceCopy *c = nullptr;
+    for (DeviceCopy *x : a->copies)
+        if (x->device == dev) c = x;
+    if (!c) return PFAC_EINVAL;  // not on this device yet: pfac_upload allocates, this call does not
+    uint8_t *base = nullptr;
+    int rc = scratch_address(dev, &base);
+    if (rc) return rc;
+    if (n == 0 || a->n_pats == 0) return launch_set_u64(d_count, 0, s) ? PFAC_EHIP : PFAC_OK;
+    // the span length chosen by text size, lengthened until the spans fit the scratch
+    // (results do not depend on it); a tuned length is kept as it is
+    uint32_t span_log2 = a->span_log2 ? a->span_log2 : auto_span_log2(n, (uint64_t)c->cus * kWaves);
+    auto spans = [&](uint32_t sl) { return (n + (1ull << sl) - 1) >> sl; };
+    if (!a->span_log2)
+        while (spans(span_log2) > kNoAllocSpans && span_log2 < kMaxSpanLog2) span_log2++;
+    const uint64_t ns = spans(span_log2);
+    if (ns > kNoAllocSpans) return PFAC_ETOO_LARGE;  // more spans than the scratch holds
+    SpanOut so{};
+    so.rec = (uint64_t *)base;
+    so.cnt = (uint64_t *)(base + kNoAllocRecBytes);
+    so.nh = (uint32_t *)(base + kNoAllocRecBytes + (uint64_t)kNoAllocSpans * 8);
+    so.ovf = (uint32_t *)(base + kNoAllocRecBytes + (uint64_t)kNoAllocSpans * 12);
+    so.rec_log2 = kNoAllocRecLog2;  // fewer records than a workspace keeps: a span past them is walked again
+    TileState ts{};
+    ts.word = (uint64_t *)(base + kNoAllocRecBytes + (uint64_t)kNoAllocSpans * 16);
+    ts.ctrl = (uint32_t *)(base + kNoAllocRecBytes + (uint64_t)kNoAllocSpans * 16 +
+                           (uint64_t)(kNoAllocSpans / kBlockSpans) * 8);
+    const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, (ns + kWaves - 1) / kWaves) : 0u;
+    // every span's count, record count and overflow are written by the count kernel
+    // before the placement reads them, and placement of this many spans uses no
+    // look-back state: nothing in the array needs clearing between calls
+    if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, d_count, so, ts, nullptr, grid, span_log2, s))
+        return PFAC_EHIP;
+    return PFAC_OK;
 }
 
 // ------------------------------------------------------------------ captured graphs

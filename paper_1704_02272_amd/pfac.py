@@ -127,6 +127,7 @@ def lib():
             "pfac_load": (C.c_int, [P8, C.c_uint64, C.POINTER(VP)]),
             "pfac_key_to_packet": (C.c_int, [P64, C.c_uint64, P64, C.c_uint32, P32, P32, P32]),
             "pfac_scan_async": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
+            "pfac_scan_noalloc": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
             "pfac_scan": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, P64, VP]),
             "pfac_scan_batch_async": (C.c_int, [VP, VP, VP, C.c_uint32, C.c_uint64, VP, C.c_uint64,
                                                 VP, VP]),
@@ -328,6 +329,16 @@ def pfac_scan_async(a: Automaton, text, keys, count, stream=None):
                                C.c_void_p(keys.data_ptr() if keys.numel() else 0), keys.numel(),
                                C.c_void_p(count.data_ptr()), _stream_handle(stream))
     _check(rc, "pfac_scan_async")
+
+
+def pfac_scan_noalloc(a: Automaton, text, keys, count, stream=None):
+    """Enqueue a scan that allocates nothing (the library's fixed per-device scratch;
+    the automaton must already be on the device). Arguments as ``pfac_scan_async``."""
+    text = _device_u8(text)
+    rc = lib().pfac_scan_noalloc(a.handle, C.c_void_p(text.data_ptr()), text.numel(),
+                                 C.c_void_p(keys.data_ptr() if keys.numel() else 0), keys.numel(),
+                                 C.c_void_p(count.data_ptr()), _stream_handle(stream))
+    _check(rc, "pfac_scan_noalloc")
 
 
 def pfac_scan(a: Automaton, text, keys=None, stream=None):
