@@ -402,6 +402,60 @@ def bench_sizes(args):
     print(json.dumps({"mode": "sizes", "rows": rows}), flush=True)
 
 
+def bench_prefix(args):
+    """Prefix-length study (Section 4.2, Fig. 3 shape): for alphabets 4, 8, ..., 52 (and
+    256), 100 random 20-symbol patterns planted once each into five seeded texts of
+    uniform symbols. The library's prefix-depth histogram gives, for every prefix length
+    k, how many starts a trie truncated after k levels (Section 2.4) lets through; those
+    beyond the full matches are false positives. Reported per alphabet: the smallest k
+    with no false positive in a file (mean over the files), the false-positive rate at
+    several k, and the uniform-text estimate n * P * |Sigma|^-k of the false positives.
+    The histogram of the first file of each alphabet is checked against the oracle on a
+    1 MiB slice."""
+    import numpy as np
+    import torch
+
+    import paper_1704_02272_amd.pfac as pfac
+    from oracle import prefix as oprefix
+
+    dev = torch.device("cuda:0")
+    n = args.sweep_mib << 20
+    L, P, cap = 20, 100, 24
+    rows = []
+    for alphabet in list(range(4, 53, 4)) + [256]:
+        pats = equal_length_patterns(alphabet, P, L, seed=alphabet * 7919 + P)
+        a = pfac.pfac_build(pats, alphabet)
+        kstar, fp_at = [], {k: [] for k in (3, 4, 5, 6, 8, 10, 12, 14, 16)}
+        for f in range(args.sweep_files):
+            rng = np.random.default_rng(20_000 + alphabet * 10 + f)
+            host = rng.integers(0, alphabet, size=n, dtype=np.uint8)
+            for j, p in enumerate(pats):  # each pattern once
+                o = int(rng.integers(0, n - L))
+                host[o:o + L] = np.frombuffer(p, np.uint8)
+            text = torch.from_numpy(host).to(dev)
+            h = pfac.pfac_prefix_histogram(a, text, cap).cpu().tolist()
+            if f == 0:
+                sl = host[: 1 << 20]
+                if pfac.pfac_prefix_histogram(a, text[: 1 << 20], cap).cpu().tolist() != \
+                        oprefix.depth_histogram(pats, sl, cap):
+                    raise RuntimeError("prefix histogram differs from the oracle at alphabet %d" % alphabet)
+            full = sum(h[L:])
+            fp = [sum(h[k:]) - full for k in range(cap + 1)]
+            kstar.append(next(k for k in range(1, L + 1) if fp[k] == 0))
+            for k in fp_at:
+                fp_at[k].append(fp[k] / n)
+            del text
+        rows.append({"alphabet": alphabet, "patterns": P, "length": L, "full_matches_per_file": full,
+                     "k_no_false_positive_mean": round(float(np.mean(kstar)), 2),
+                     "k_no_false_positive_per_file": kstar,
+                     "false_positive_rate": {str(k): float("%.3g" % np.mean(v)) for k, v in fp_at.items()},
+                     "uniform_estimate_fp_at_k": {str(k): float("%.3g" % (n * P * float(alphabet) ** -k))
+                                                  for k in fp_at}})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"mode": "prefix", "text_mib": args.sweep_mib, "files": args.sweep_files,
+                      "rows": rows}), flush=True)
+
+
 def bench_sweep(args):
     """Throughput over alphabets and pattern counts (Section 4.3, Figs. 7-9 shape): for
     every alphabet in 4, 8, ..., 52 and 256 and every count in 1, 10, 100, 1,000 of
@@ -507,7 +561,7 @@ def main():
     ap.add_argument("--sweep-files", type=int, default=5, help="sweep: seeded texts per alphabet")
     ap.add_argument("--baseline-steps", type=int, default=3,
                     help="packets: timed passes of the per-packet baseline")
-    ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host", "sizes", "sweep"],
+    ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host", "sizes", "sweep", "prefix"],
                     help="copy: a plain device-to-device copy of the workload's text, the "
                          "reference that scales the HBM byte counters of the scan; host: the "
                          "text starts in host memory (pinned, then pageable) and crosses PCIe "
@@ -529,6 +583,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "prefix":
+        bench_prefix(args)
+        return
     if args.mode == "sweep":
         bench_sweep(args)
         return

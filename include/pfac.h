@@ -280,6 +280,18 @@ PFAC_API int pfac_scan_host(pfac_automaton *a, const uint8_t *h_text, uint64_t n
 /* Free the array of a pfac_matches (and zero it). NULL is a no-op. */
 PFAC_API void pfac_matches_free(pfac_matches *m);
 
+/* pfac_prefix_histogram -- prefix depths of a text (device memory, n bytes): for every
+ * start s, the number of symbols a failure-less walk from s consumes before a transition
+ * is missing (Section 2.3), i.e. the length of the longest pattern prefix spelled at s,
+ * capped at cap. Writes hist[d] = number of starts of depth d for d < cap and hist[cap] =
+ * starts of depth cap or more (device memory, cap + 1 uint64 entries, zeroed by the
+ * call). A trie truncated after k levels (Section 2.4) passes exactly the starts of depth
+ * >= k; Section 4.2 studies how large k must be for an alphabet before those are only the
+ * real matches. Stream-ordered like pfac_scan_async. Errors: PFAC_EINVAL (NULL
+ * arguments, cap outside 1..63), PFAC_ENODEVICE, PFAC_ENOMEM, PFAC_EHIP. */
+PFAC_API int pfac_prefix_histogram(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint32_t cap,
+                                   uint64_t *d_hist, void *stream);
+
 /* ------------------------------------------------------------------- packet batches
  * pfac_scan_batch_async -- scan a batch of packets held back to back in device memory
  * (CSR): packet i is d_bytes[d_offsets[i] .. d_offsets[i+1]), with d_offsets[0] = 0,

@@ -20,6 +20,9 @@ Contents
 * ``reduce``   -- the trie compression of Section 3.2 as a node count (merging nodes of
                   the bottom levels whose suffixes agree; Eq. 2; Eqs. 3-4 read as an
                   occupancy law).
+* ``prefix``   -- prefix depths: for every start, the longest pattern prefix the text
+                  spells there, as a histogram (the quantity behind the truncated trie
+                  of Section 2.4 and the prefix-length study of Section 4.2).
 
 Parity status: every function here is pinned by tests under ``tests/`` against hand
 derived answers, printed values of the paper, closed forms and cross-algorithm checks.

@@ -53,7 +53,7 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     const uint32_t bits = t.pack2 ? 2 : 8;
     if (a->n_pats == 0) {
         t.root_depth = t.root_bits = t.root_base = 0;
-        t.filter_k = t.filter_log2 = t.has_short = t.sampled = 0;
+        t.filter_k = t.filter_log2 = t.has_short = t.sampled = t.exact = 0;
         t.lds_words = t.root_word = t.rank_word = t.short_word = 0;
         a->lds_image.clear();
         return;
@@ -73,6 +73,46 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     // the long K-grams' false-positive share of the filter bits (one bit per key), plus
     // their true share of all K-grams. Ties go to the longer key.
     const uint32_t kcap = std::min(kmax, a->max_len);
+    // Two-bit symbols: by default (and whenever a key of D + 1 symbols is asked for) the
+    // filter is exact, the trie's first D + 1 levels as a direct bitmap (the exact form).
+    if (t.pack2 && (reqK == 0 || reqK == D + 1)) {
+        const uint32_t K1 = D + 1, kbits = 2 * K1;
+        const uint32_t fwords = std::max<uint32_t>(4, (1u << kbits) / 32);  // whole 16-byte units
+        t.filter_k = K1;
+        t.filter_log2 = kbits;
+        t.has_short = 0;
+        t.sampled = 0;
+        t.exact = 1;
+        t.root_word = fwords;
+        t.rank_word = fwords + root_words;
+        t.short_word = t.rank_word + rank_words;
+        t.lds_words = t.short_word;
+        a->lds_image.assign(t.lds_words, 0);
+        uint32_t *img = a->lds_image.data();
+        uint32_t *root = img + t.root_word;
+        for (uint32_t j = 0; j < a->n_pats; j++) {
+            const uint32_t key = root_key(P[j], D, bits);
+            root[key >> 5] |= 1u << (key & 31);
+            if (a->pat_len[j] > D) {
+                const uint32_t k1 = root_key(P[j], K1, bits);
+                img[k1 >> 5] |= 1u << (k1 & 31);
+            } else {  // a whole pattern of D symbols: every next symbol passes
+                for (uint32_t x = 0; x < 4; x++) {
+                    const uint32_t k1 = (key << 2) | x;
+                    img[k1 >> 5] |= 1u << (k1 & 31);
+                }
+            }
+        }
+        uint16_t *rank = reinterpret_cast<uint16_t *>(img + t.rank_word);
+        uint32_t run = 0;
+        for (uint32_t w = 0; w < root_words; w++) {
+            rank[w] = (uint16_t)run;
+            run += (uint32_t)__builtin_popcount(root[w]);
+        }
+        if (run != a->depth_start[D + 1] - a->depth_start[D]) throw std::bad_alloc();
+        return;
+    }
+    t.exact = 0;
     uint32_t K = D;
     double best = 1e30;
     for (uint32_t k = reqK ? reqK : D; k <= (reqK ? reqK : kcap); k++) {

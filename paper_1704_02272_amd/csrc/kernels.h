@@ -14,6 +14,11 @@ int launch_plain(const DevTable &t, const uint8_t *text, uint64_t n, uint64_t *k
                  uint64_t *block_offsets, hipStream_t s);
 uint64_t plain_blocks(uint64_t n);
 
+// Histogram of prefix depths (walk steps before a missing transition, capped at cap,
+// 1 <= cap <= 63) of every start of text[0 .. n) into hist[0 .. cap], zeroed first.
+int launch_prefix_hist(const DevTable &t, const uint8_t *text, uint64_t n, uint32_t cap, uint64_t *hist,
+                       uint32_t cus, hipStream_t s);
+
 // Store one value to device memory (graph-capture safe: a kernel, not a memset).
 int launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t s);
 

@@ -9,6 +9,8 @@
 //
 // This path is kept as the in-library baseline the optimized scan is measured against
 // (same output, bit for bit); it is selected with PFAC_ALGO_PLAIN.
+#include <algorithm>
+
 #include "pfac_impl.h"
 #include "kernels.h"
 
@@ -176,6 +178,41 @@ __global__ __launch_bounds__(kPlainThreads) void plain_emit(DevTable t, const ui
     }
 }
 
+// Prefix depths (Section 2.4's truncated trie, Section 4.2's study): for every start the
+// number of Eq. 1 steps the walk takes before a transition is missing, capped at `cap`,
+// gathered into hist[0 .. cap] (the last bin: depth cap or more). One lane per start,
+// grid-stride; each workgroup keeps its bins in LDS and adds them to hist once.
+constexpr uint32_t kHistMaxBins = 64;
+
+__global__ void hist_zero(uint64_t *hist, uint32_t bins) {
+    for (uint32_t i = threadIdx.x; i < bins; i += blockDim.x) hist[i] = 0;
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(kPlainThreads) void prefix_hist(DevTable t, const uint8_t *text, uint64_t n,
+                                                             uint32_t cap, uint64_t *hist) {
+    __shared__ uint32_t bins[kHistMaxBins];
+    for (uint32_t i = threadIdx.x; i < kHistMaxBins; i += kPlainThreads) bins[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * kPlainThreads;
+    for (uint64_t s = (uint64_t)blockIdx.x * kPlainThreads + threadIdx.x; s < n; s += stride) {
+        uint32_t q = 0, d = 0;
+        for (uint64_t p = s; p < n && d < cap; p++) {
+            const uint32_t c = text[p];
+            if (c >= t.alphabet) break;
+            bool term = false;
+            const int64_t nq = step<LAYOUT>(t, q, c, term);
+            if (nq < 0) break;
+            q = (uint32_t)nq;
+            d++;
+        }
+        atomicAdd(&bins[d], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i <= cap; i += kPlainThreads)
+        if (bins[i]) atomicAdd((unsigned long long *)&hist[i], (unsigned long long)bins[i]);
+}
+
 }  // namespace
 
 int launch_plain(const DevTable &t, const uint8_t *text, uint64_t n, uint64_t *keys,
@@ -192,6 +229,21 @@ int launch_plain(const DevTable &t, const uint8_t *text, uint64_t n, uint64_t *k
         plain_emit<LAYOUT_NARROW><<<(unsigned)nb, kPlainThreads, 0, s>>>(t, text, n, block_offsets, keys, cap);
     else
         plain_emit<LAYOUT_WIDE><<<(unsigned)nb, kPlainThreads, 0, s>>>(t, text, n, block_offsets, keys, cap);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prefix_hist(const DevTable &t, const uint8_t *text, uint64_t n, uint32_t cap, uint64_t *hist,
+                       uint32_t cus, hipStream_t s) {
+    if (cap == 0 || cap >= kHistMaxBins) return -1;
+    hist_zero<<<1, 64, 0, s>>>(hist, cap + 1);
+    const uint64_t want = (n + kPlainThreads - 1) / kPlainThreads;
+    const uint64_t grid = std::min<uint64_t>(want ? want : 1, (uint64_t)cus * 8);
+    if (n) {
+        if (t.layout == LAYOUT_NARROW)
+            prefix_hist<LAYOUT_NARROW><<<(unsigned)grid, kPlainThreads, 0, s>>>(t, text, n, cap, hist);
+        else
+            prefix_hist<LAYOUT_WIDE><<<(unsigned)grid, kPlainThreads, 0, s>>>(t, text, n, cap, hist);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

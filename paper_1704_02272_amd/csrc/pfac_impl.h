@@ -68,6 +68,8 @@ struct DevTable {
     uint32_t has_short;         // 1: some pattern is shorter than k (short bitmap used)
     uint32_t filter_log2;       // log2(bits of the first-probe region); 0 = no filter
     uint32_t sampled;           // 1: sampled prefilter layout (every second start probed)
+    uint32_t exact;             // 1: exact form: the filter is the (D+1)-symbol bitmap (two-bit
+                                //    symbols, filter_k = D + 1)
     uint32_t lds_words;         // total image size in 32-bit words
     uint32_t root_word;         // word offset of the root bitmap
     uint32_t rank_word;         // word offset of the rank table

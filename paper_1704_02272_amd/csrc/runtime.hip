@@ -441,6 +441,17 @@ extern "C" int pfac_scan_noalloc(pfac_automaton *a, const uint8_t *d_text, uint6
     return PFAC_OK;
 }
 
+// ------------------------------------------------------------------ prefix depths
+extern "C" int pfac_prefix_histogram(pfac_automaton *a, const uint8_t *d_text, uint64_t n, uint32_t cap,
+                                     uint64_t *d_hist, void *stream) {
+    if (!a || !d_hist || (n > 0 && !d_text) || cap == 0 || cap > 63) return PFAC_EINVAL;
+    std::lock_guard<std::mutex> g(a->mu);
+    DeviceCopy *c = nullptr;
+    int rc = get_copy(a, &c);
+    if (rc) return rc;
+    return launch_prefix_hist(c->view, d_text, n, cap, d_hist, c->cus, (hipStream_t)stream) ? PFAC_EHIP : PFAC_OK;
+}
+
 // ------------------------------------------------------------------ captured graphs
 struct pfac_graph {
     pfac_automaton *a = nullptr;

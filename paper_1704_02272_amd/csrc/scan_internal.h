@@ -61,7 +61,12 @@ static_assert((1u << kStepLog2) == kStep, "step length is a power of two");
 //             two-probe Bloom filter over k-gram keys, every start probed; the short
 //             bitmap holds the D-grams of patterns shorter than k
 //   sampled   [second-probe part: 2^16 bits][first-probe part: 2^17 bits][3-gram part: 2^19 bits]
-//             [root bitmap][rank table][survivor queues, 512 entries a wave]
+//             [root bitmap][rank table][step staging, 576 words a wave]
+//             [survivor queues, 512 entries a wave]
+//   exact     [(D+1)-symbol bitmap: up to 2^18 bits][root bitmap][rank table]
+//             [survivor queues, 512 entries a wave]
+//             two-bit symbols: every start probed once in an exact bitmap of the trie's
+//             first D+1 levels (no hash, no false positive beyond the truncation)
 //             patterns of four or more bytes and k = 4: only every second start is
 //             probed, with the 3-gram there against the 3-grams at offsets 0 and 1 of
 //             every pattern; the two starts it stands for are then checked against the
@@ -87,10 +92,12 @@ constexpr uint32_t kFilterMul3 = 0x9E3779u;  // 24-bit multiplier of the 3-gram 
 constexpr uint32_t kRootWordsMax = 1u << 11;    // 8 KiB: root keys up to 16 bits
 constexpr uint32_t kRankWordsMax = 1u << 10;    // 4 KiB: one u16 per root word
 
-template <bool SAMPLED>
+// LDS layouts (see above), one per prefilter form.
+enum LdsForm : int { kFormGeneral = 0, kFormSampled = 1, kFormExact = 2 };
+template <int FORM>
 struct Lds;
 template <>
-struct Lds<false> {
+struct Lds<kFormGeneral> {
     static constexpr uint32_t shrt = kGeneralWords;
     static constexpr uint32_t root = shrt + kRootWordsMax;
     static constexpr uint32_t rank = root + kRootWordsMax;
@@ -98,17 +105,39 @@ struct Lds<false> {
     static constexpr uint32_t queues = rank + kRankWordsMax;
     static constexpr uint32_t words = queues + kWaves * qcap / 2;
 };
+// The sampled layout also stages each lane's bytes of the current step (its 32 bytes and
+// the 4 after them: 9 words at a stride of 9 words per lane, so the 32 lanes of a bank
+// group read distinct banks) for the candidate checks.
+constexpr uint32_t kStageLaneWords = 9;
+constexpr uint32_t kStageWords = 64 * kStageLaneWords;
 template <>
-struct Lds<true> {
+struct Lds<kFormSampled> {
     static constexpr uint32_t root = kSampledWords;
     static constexpr uint32_t rank = root + kRootWordsMax;
     static constexpr uint32_t shrt = 0;  // none: no pattern is shorter than k
     static constexpr uint32_t qcap = PFAC_QCAP;
+    static constexpr uint32_t stage = rank + kRankWordsMax;
+    static constexpr uint32_t queues = stage + kWaves * kStageWords;
+    static constexpr uint32_t words = queues + kWaves * qcap / 2;
+};
+// Exact form (two-bit symbols): the trie truncated one level below the root image, as a
+// direct bitmap over (D+1)-symbol keys: a key's bit is set when some pattern begins with
+// it, or when its first D symbols are a whole pattern (every extension of a pattern of
+// length D is set). 4^(D+1) bits, at most 2^18 (32 KiB, D = 8).
+constexpr uint32_t kExactWordsMax = 1u << 13;
+template <>
+struct Lds<kFormExact> {
+    static constexpr uint32_t root = kExactWordsMax;
+    static constexpr uint32_t rank = root + kRootWordsMax;
+    static constexpr uint32_t shrt = 0;  // none
+    static constexpr uint32_t qcap = PFAC_QCAP;
     static constexpr uint32_t queues = rank + kRankWordsMax;
     static constexpr uint32_t words = queues + kWaves * qcap / 2;
 };
-static_assert(Lds<false>::qcap >= 128 && Lds<false>::qcap % 8 == 0, "a queue holds two walk batches");
-static_assert(Lds<false>::words * 4 <= 160 * 1024 && Lds<true>::words * 4 <= 160 * 1024, "LDS of one CU");
+static_assert(Lds<kFormGeneral>::qcap >= 128 && Lds<kFormGeneral>::qcap % 8 == 0, "a queue holds two walk batches");
+static_assert(Lds<kFormGeneral>::words * 4 <= 160 * 1024 && Lds<kFormSampled>::words * 4 <= 160 * 1024 &&
+                  Lds<kFormExact>::words * 4 <= 160 * 1024,
+              "LDS of one CU");
 
 // Per-span results of the count kernel (device memory, owned by a workspace).
 //   cnt[s]   matches in span s          nh[s]   records stored for span s

@@ -287,7 +287,7 @@ struct Trie {
 // Walk of a survivor in the count kernel: the first D symbols through the LDS root
 // image, the rest through the trie in HBM. The first eight text bytes come from one
 // round of independent loads.
-template <int LAYOUT, bool PACK2, bool SAMPLED, bool MERGED>
+template <int LAYOUT, bool PACK2, int FORM, bool MERGED>
 struct RootWalk {
     const DevTable &t;
     const uint8_t *__restrict__ text;
@@ -307,9 +307,9 @@ struct RootWalk {
             key = (key << (PACK2 ? 2 : 8)) | c;
         }
         const uint32_t wi = key >> 5, b = key & 31;
-        const uint32_t word = img[Lds<SAMPLED>::root + wi];
+        const uint32_t word = img[Lds<FORM>::root + wi];
         if (!((word >> b) & 1u)) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + Lds<SAMPLED>::rank);
+        const uint16_t *rank = reinterpret_cast<const uint16_t *>(img + Lds<FORM>::rank);
         uint32_t q = t.root_base + rank[wi] + __builtin_popcount(word & ((1u << b) - 1u));
         // continue with the bytes already loaded, then one load per level
         const Trie<LAYOUT, MERGED> T{t};
@@ -440,8 +440,16 @@ __device__ __forceinline__ uint32_t probe_root(const uint32_t *root, uint32_t ke
 
 // Prefilter forms, fixed per kernel instance: FM_K4 four-byte keys and no pattern shorter
 // than four (the sampled layout); FM_GEN any key length, with the short-pattern bitmap;
-// FM_ROOT no hashed filter (the root image's D-gram bitmap is the test).
-enum FilterMode : int { FM_K4 = 0, FM_GEN = 1, FM_ROOT = 2 };
+// FM_ROOT no hashed filter (the root image's D-gram bitmap is the test); FM_EXACT two-bit
+// symbols, the exact bitmap of the first D + 1 trie levels (the exact layout).
+enum FilterMode : int { FM_K4 = 0, FM_GEN = 1, FM_ROOT = 2, FM_EXACT = 3 };
+
+// LDS layout of a kernel instance.
+template <bool PACK2, int FM>
+struct FormOf {
+    static constexpr int value = (FM == FM_K4 && !PACK2) ? kFormSampled : (FM == FM_EXACT && PACK2) ? kFormExact
+                                                                                                   : kFormGeneral;
+};
 
 // Prefilter mask of 16 starts of a lane (bit j = the start at byte j of cur): the
 // survivors, or for FM_K4 the candidates (odd j only; see sample_step). cur: the 16
@@ -469,7 +477,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         } else if (FM == FM_GEN) {
             // k-gram filter, plus the short bitmap for patterns shorter than k
             const uint32_t kmask = t.filter_k >= 4 ? 0xffffffffu : (1u << (8 * t.filter_k)) - 1u;
-            const uint32_t *shrt = img + Lds<false>::shrt;
+            const uint32_t *shrt = img + Lds<kFormGeneral>::shrt;
             const bool two = t.root_depth == 2, sh = t.has_short;
             uint32_t ms = 0;
 #pragma unroll
@@ -490,7 +498,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
             mask |= ms;
         } else {
             // root image as the filter: D-byte key, first byte most significant
-            const uint32_t *root = img + Lds<false>::root;
+            const uint32_t *root = img + Lds<kFormGeneral>::root;
             const bool two = t.root_depth == 2;
 #pragma unroll
             for (int j = 15; j >= 0; j--) {
@@ -503,9 +511,16 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
         // window of K symbols at j: the top 2K bits of symbols j..j+15
         const uint32_t K = FM != FM_ROOT ? t.filter_k : t.root_depth;
         const uint32_t rs = 32 - 2 * K;
-        if (FM != FM_ROOT) {
+        if (FM == FM_EXACT) {
+            // one probe per start: bit (symbols j .. j+K-1) of the exact bitmap at offset 0
+#pragma unroll
+            for (int j = 15; j >= 0; j--) {
+                const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
+                mask = (mask << 1) | probe_root(img, top >> rs);
+            }
+        } else if (FM != FM_ROOT) {
             // k-gram filter, plus the short bitmap (D-grams) for patterns shorter than k
-            const uint32_t *shrt = img + Lds<false>::shrt;
+            const uint32_t *shrt = img + Lds<kFormGeneral>::shrt;
             const uint32_t rsd = 32 - 2 * t.root_depth;
             const bool sh = t.has_short;
             uint32_t ms = 0;
@@ -524,7 +539,7 @@ __device__ __forceinline__ uint32_t prefilter16(const DevTable &t, const uint32_
             }
             mask |= ms;
         } else {
-            const uint32_t *root = img + Lds<false>::root;
+            const uint32_t *root = img + Lds<kFormGeneral>::root;
 #pragma unroll
             for (int j = 15; j >= 0; j--) {
                 const uint32_t top = j ? __builtin_amdgcn_alignbit(c0, c1, 32 - 2 * j) : c0;
@@ -550,8 +565,9 @@ template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED>
 struct Scanner {
     const DevTable &t;
     static constexpr bool kSampled = FM == FM_K4 && !PACK2;
-    static constexpr uint32_t kQ = Lds<kSampled>::qcap;  // survivor queue entries
-    RootWalk<LAYOUT, PACK2, kSampled, MERGED> W;
+    static constexpr int kForm = FormOf<PACK2, FM>::value;
+    static constexpr uint32_t kQ = Lds<kForm>::qcap;  // survivor queue entries
+    RootWalk<LAYOUT, PACK2, kForm, MERGED> W;
     const uint8_t *__restrict__ text;
     uint64_t n, lim;  // starts >= lim cannot match (too little text left)
     const uint64_t *__restrict__ offsets;
@@ -559,6 +575,7 @@ struct Scanner {
     SpanOut so;
     uint16_t *q;  // survivor queue (span-local starts), kQ entries
     bool aligned;
+    uint32_t *stg;  // sampled form: this wave's step staging words (kStageWords)
 
     // A lane's bytes of one step: kLaneBytes (16 or 32) consecutive text bytes, with the
     // two-bit codes of each 16 when symbols are two-bit codes.
@@ -691,24 +708,13 @@ struct Scanner {
         push(q, S.qlen, kQ, m, sl0, [&] { drain(S); });
     }
 
-    // The two words holding bytes j-1 .. j+3 of a lane's step bytes d[0..8] (j odd, so
-    // j-1 is even and the five bytes never span three words): d[q], d[q+1] with
-    // q = (j-1) >> 2, picked by a select tree on the bits of q (a register cannot be
-    // indexed by a value that differs between lanes).
-    __device__ __forceinline__ static void window2(const uint32_t (&d)[9], uint32_t j, uint32_t &lo, uint32_t &hi) {
-        // bits 2..4 of j are those of j-1 (j-1 is even); bit 4 as a compare
-        const bool b2 = j >= 16u, b1 = (j & 8u) != 0, b0 = (j & 4u) != 0;
-        const uint32_t e0 = b2 ? d[4] : d[0], e1 = b2 ? d[5] : d[1], e2 = b2 ? d[6] : d[2], e3 = b2 ? d[7] : d[3];
-        const uint32_t f3 = b2 ? d[8] : d[4];
-        const uint32_t g0 = b1 ? e2 : e0, g1 = b1 ? e3 : e1, h1 = b1 ? f3 : e2;
-        lo = b0 ? g1 : g0;
-        hi = b0 ? h1 : g1;
-    }
-
-    // Both 4-gram probes of the starts j-1 and j (bits j-1 and j of the result).
-    __device__ __forceinline__ uint32_t check2(const uint32_t (&d)[9], uint32_t j) const {
-        uint32_t lo, hi;
-        window2(d, j, lo, hi);
+    // Both 4-gram probes of the starts j-1 and j (bits j-1 and j of the result). The two
+    // words holding bytes j-1 .. j+3 (j odd, so j-1 is even and the five bytes never span
+    // three words) are read back from the lane's staged step bytes: words q and q + 1,
+    // q = (j - 1) >> 2, one LDS read for a choice a register file cannot index per lane.
+    __device__ __forceinline__ uint32_t check2(const uint32_t *my, uint32_t j) const {
+        const uint32_t q = (j - 1) >> 2;
+        const uint32_t lo = my[q], hi = my[q + 1];
         // k0 = bytes j-1..j+2, k1 = bytes j..j+3: k0 >> 8 equals k1 in the 24 bits a
         // 24-bit multiply reads (and in its low byte), so k1 stands in for it
         const uint32_t k0 = __builtin_amdgcn_alignbyte(hi, lo, (j - 1) & 3u);
@@ -726,17 +732,27 @@ struct Scanner {
                                                 uint32_t m, uint32_t sl0) {
         static_assert(kLaneBytes == 32, "the sampled check reads a lane's 32 bytes");
         if (!__ballot(m != 0)) return;
-        const uint32_t d[9] = {cur.v[0].x, cur.v[0].y, cur.v[0].z, cur.v[0].w,
-                               cur.v[1].x, cur.v[1].y, cur.v[1].z, cur.v[1].w, nd};
+        // the lane's 36 bytes to its staging words (read back only by this lane; the
+        // wave's LDS operations complete in order, so no barrier is needed either way)
+        uint32_t *my = stg + kStageLaneWords * lane_id();
+        my[0] = cur.v[0].x;
+        my[1] = cur.v[0].y;
+        my[2] = cur.v[0].z;
+        my[3] = cur.v[0].w;
+        my[4] = cur.v[1].x;
+        my[5] = cur.v[1].y;
+        my[6] = cur.v[1].z;
+        my[7] = cur.v[1].w;
+        my[8] = nd;
         const uint32_t m2 = m & (m - 1), m3 = m2 & (m2 - 1);
         uint32_t sm = 0;
         if (m) {  // only lanes with candidates probe (fewer LDS bank conflicts)
-            sm = check2(d, (uint32_t)__builtin_ctz(m));
-            if (m2) sm |= check2(d, (uint32_t)__builtin_ctz(m2));
+            sm = check2(my, (uint32_t)__builtin_ctz(m));
+            if (m2) sm |= check2(my, (uint32_t)__builtin_ctz(m2));
         }
         for (uint32_t r = m3; __ballot(r != 0);) {
             const uint32_t j = r ? (uint32_t)__builtin_ctz(r) : 1u;
-            const uint32_t s = check2(d, j);
+            const uint32_t s = check2(my, j);
             sm |= r ? s : 0u;
             r &= r - 1;
         }
@@ -880,7 +896,7 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
                                                       const uint64_t *__restrict__ offsets, uint32_t n_packets,
                                                       SpanOut so, const uint64_t *__restrict__ sizes,
                                                       uint32_t span_log2) {
-    using L = Lds<FM == FM_K4 && !PACK2>;
+    using L = Lds<FormOf<PACK2, FM>::value>;
     __shared__ __align__(16) uint32_t img[L::words];
     if (sizes) {  // sizes of this batch, bounded by those the launch was set up for
         n = sizes[0] < n ? sizes[0] : n;
@@ -932,8 +948,10 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     // load offsets) then stays in scalar registers
     const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint16_t *wq = reinterpret_cast<uint16_t *>(img + L::queues) + wave * L::qcap;
+    uint32_t *stg = nullptr;
+    if constexpr (FormOf<PACK2, FM>::value == kFormSampled) stg = img + L::stage + wave * kStageWords;
     Scanner<LAYOUT, PACK2, SEG, FM, MERGED> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
-                                   offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0};
+                                   offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0, stg};
     const uint32_t waves = gridDim.x * kWaves;
     for (uint32_t span = blockIdx.x * kWaves + wave; span < n_spans; span += waves) {
         SpanState S{(uint64_t)span << span_log2, span, 0, 0, kNone, 0};
@@ -1279,24 +1297,32 @@ int launch_tiled_t(const DevTable &t, const uint8_t *text, uint64_t n, const uin
     const bool seg = offsets != nullptr;
     const bool narrow = t.layout == LAYOUT_NARROW;
     const bool pack2 = t.pack2 != 0;
-    const int fm = t.filter_k == 0 ? FM_ROOT : t.sampled ? FM_K4 : FM_GEN;
+    const int fm = t.filter_k == 0 ? FM_ROOT : t.sampled ? FM_K4 : t.exact ? FM_EXACT : FM_GEN;
 #define PFAC_L(LA, P2, SG, F) \
     return launch_one<LA, P2, SG, F, MERGED>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, \
                                              span_log2, s)
-#define PFAC_FM(LA, P2, SG)                                    \
+    // two-bit symbols: the exact, hashed and root-only forms; bytes: sampled, hashed, root-only
+#define PFAC_FM2(LA, SG)                                       \
     do {                                                       \
-        if (fm == FM_ROOT) PFAC_L(LA, P2, SG, FM_ROOT);        \
-        if (fm == FM_GEN || P2) PFAC_L(LA, P2, SG, FM_GEN);    \
-        PFAC_L(LA, P2, SG, FM_K4);                             \
+        if (fm == FM_ROOT) PFAC_L(LA, true, SG, FM_ROOT);      \
+        if (fm == FM_EXACT) PFAC_L(LA, true, SG, FM_EXACT);    \
+        PFAC_L(LA, true, SG, FM_GEN);                          \
+    } while (0)
+#define PFAC_FM(LA, SG)                                        \
+    do {                                                       \
+        if (fm == FM_ROOT) PFAC_L(LA, false, SG, FM_ROOT);     \
+        if (fm == FM_GEN) PFAC_L(LA, false, SG, FM_GEN);       \
+        PFAC_L(LA, false, SG, FM_K4);                          \
     } while (0)
     if (narrow) {
-        if (pack2) { if (seg) PFAC_FM(LAYOUT_NARROW, true, true); else PFAC_FM(LAYOUT_NARROW, true, false); }
-        else { if (seg) PFAC_FM(LAYOUT_NARROW, false, true); else PFAC_FM(LAYOUT_NARROW, false, false); }
+        if (pack2) { if (seg) PFAC_FM2(LAYOUT_NARROW, true); else PFAC_FM2(LAYOUT_NARROW, false); }
+        else { if (seg) PFAC_FM(LAYOUT_NARROW, true); else PFAC_FM(LAYOUT_NARROW, false); }
     } else {
-        if (seg) PFAC_FM(LAYOUT_WIDE, false, true);
-        PFAC_FM(LAYOUT_WIDE, false, false);
+        if (seg) PFAC_FM(LAYOUT_WIDE, true);
+        PFAC_FM(LAYOUT_WIDE, false);
     }
 #undef PFAC_FM
+#undef PFAC_FM2
 #undef PFAC_L
 }
 

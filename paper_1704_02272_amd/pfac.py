@@ -128,6 +128,7 @@ def lib():
             "pfac_key_to_packet": (C.c_int, [P64, C.c_uint64, P64, C.c_uint32, P32, P32, P32]),
             "pfac_scan_async": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
             "pfac_scan_noalloc": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, VP, VP]),
+            "pfac_prefix_histogram": (C.c_int, [VP, VP, C.c_uint64, C.c_uint32, VP, VP]),
             "pfac_scan": (C.c_int, [VP, VP, C.c_uint64, VP, C.c_uint64, P64, VP]),
             "pfac_scan_batch_async": (C.c_int, [VP, VP, VP, C.c_uint32, C.c_uint64, VP, C.c_uint64,
                                                 VP, VP]),
@@ -339,6 +340,19 @@ def pfac_scan_noalloc(a: Automaton, text, keys, count, stream=None):
                                  C.c_void_p(keys.data_ptr() if keys.numel() else 0), keys.numel(),
                                  C.c_void_p(count.data_ptr()), _stream_handle(stream))
     _check(rc, "pfac_scan_noalloc")
+
+
+def pfac_prefix_histogram(a: Automaton, text, cap: int, stream=None):
+    """Prefix depths of ``text`` (uint8 device tensor): int64 device tensor of cap + 1
+    bins, bin d = starts whose longest spelled pattern prefix has length d (the last bin:
+    cap or more)."""
+    import torch
+    text = _device_u8(text)
+    hist = torch.empty(cap + 1, dtype=torch.int64, device=text.device)
+    rc = lib().pfac_prefix_histogram(a.handle, C.c_void_p(text.data_ptr() if text.numel() else 0), text.numel(),
+                                     cap, C.c_void_p(hist.data_ptr()), _stream_handle(stream))
+    _check(rc, "pfac_prefix_histogram")
+    return hist
 
 
 def pfac_scan(a: Automaton, text, keys=None, stream=None):
