@@ -259,7 +259,8 @@ def bench_serving(args):
 
     w = W.serving_256(duration_s=args.serve_seconds, contiguous=True, plant_every=args.plant_every)
     a = pfac.pfac_build(w.patterns, w.alphabet)
-    srv = pfac.pfac_server_create(a, slots=args.slots, max_batch_bytes=args.batch_mib << 20)
+    srv = pfac.pfac_server_create(a, slots=args.slots, max_batch_bytes=args.batch_mib << 20,
+                                  flags=pfac.PFAC_SERVER_EAGER if args.eager else 0)
     cfg = srv.config()
     ptrs = [(r.data.ctypes.data, r.offsets.ctypes.data, int(r.offsets[-1])) for r in w.requests]
     arr_ns = [int(r.arrival_s * 1e9) for r in w.requests]
@@ -555,6 +556,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="serving: batch slots")
     ap.add_argument("--batch-mib", type=int, default=8, help="serving: MiB per batch")
     ap.add_argument("--plant-every", type=int, default=0, help="serving: planted variant")
+    ap.add_argument("--eager", action="store_true", help="serving: eager launch pairs instead of graph replays")
     ap.add_argument("--verify", type=int, default=256,
                     help="serving: requests (evenly spread) whose keys are checked against the oracle")
     ap.add_argument("--sweep-mib", type=int, default=100, help="sweep: MiB per text")

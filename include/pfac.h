@@ -136,6 +136,10 @@ typedef struct {
     uint64_t stream_scratch;     /* per-stream scratch areas held on all devices (one
                                     per stream a scan ran on; freed with the automaton,
                                     or when the library's own streams are destroyed)    */
+    uint32_t device_records;     /* node words of the device table: the plain table
+                                    stores a unary path below the root image's levels as
+                                    one tail record, not as nodes                       */
+    uint32_t device_tails;       /* tail records of the plain table (0 when compressed) */
 } pfac_table_info_t;
 
 PFAC_API int pfac_table_info(const pfac_automaton *a, pfac_table_info_t *out);
@@ -345,7 +349,8 @@ PFAC_API void pfac_graph_destroy(pfac_graph *g);
 /* ------------------------------------------------------------------- serving loop
  * A server keeps the automaton resident on the current device and scans packet requests
  * as they arrive (continuous batching). Requests wait in a FIFO; a worker thread owns
- * `slots` batch slots, each with its own device buffers, stream and captured scan graph.
+ * `slots` batch slots, each with its own device buffers, stream and captured scan graph
+ * (or, with PFAC_SERVER_EAGER, its own scan scratch sized for a full batch).
  * Whenever a slot is free, the worker packs every waiting request that fits
  * (max_batch_bytes / max_batch_packets) into one batch and launches it at once, so
  * requests that arrive while other batches run on the GPU are admitted as slots free up,
@@ -365,8 +370,13 @@ typedef struct {
     uint64_t key_capacity;        /* keys a slot returns without a rescan (65,536)       */
     uint64_t max_pending_bytes;   /* bytes allowed to wait for a slot (1 GiB)            */
     uint64_t device_memory_budget;/* device bytes all slots may hold (0 = free / 4)      */
-    uint32_t reserved[4];
+    uint32_t flags;               /* PFAC_SERVER_EAGER: each batch is enqueued as its own
+                                     launch pair (pfac_scan_batch_async) instead of a
+                                     replay of the slot's captured graph; same results  */
+    uint32_t reserved[3];
 } pfac_server_config;
+
+#define PFAC_SERVER_EAGER 1u
 
 /* One finished request. keys: (offset of the match start within the request's bytes
  * << 32) | pattern_id, sorted; map a start to its packet with the request's offsets.

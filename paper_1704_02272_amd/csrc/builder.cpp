@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <stdexcept>
 
 #include "pfac.h"
 #include "pfac_impl.h"
@@ -73,10 +74,70 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
     // the long K-grams' false-positive share of the filter bits (one bit per key), plus
     // their true share of all K-grams. Ties go to the longer key.
     const uint32_t kcap = std::min(kmax, a->max_len);
-    // Two-bit symbols: by default (and whenever a key of D + 1 symbols is asked for) the
-    // filter is exact, the trie's first D + 1 levels as a direct bitmap (the exact form).
-    if (t.pack2 && (reqK == 0 || reqK == D + 1)) {
-        const uint32_t K1 = D + 1, kbits = 2 * K1;
+    // Estimated pass rate of a hashed filter with key length k (k == D: the root image
+    // alone). Two-bit symbols skip k == D + 1 and D + 2, which are the exact form below.
+    auto estimate = [&](uint32_t k) {
+        std::vector<uint32_t> sk, lk;
+        for (uint32_t j = 0; j < a->n_pats; j++) {
+            if (a->pat_len[j] < k) sk.push_back(root_key(P[j], D, bits));
+            else lk.push_back(filter_key(P[j], k, t.pack2));
+        }
+        std::sort(sk.begin(), sk.end());
+        sk.erase(std::unique(sk.begin(), sk.end()), sk.end());
+        std::sort(lk.begin(), lk.end());
+        lk.erase(std::unique(lk.begin(), lk.end()), lk.end());
+        const double space = std::pow((double)a->alphabet, (double)k);
+        double est = (double)sk.size() / root_nbits + (double)lk.size() / space;
+        if (k > D) est += (double)lk.size() / (double)(1u << kMaxFilterLog2) * (double)lk.size() / (double)(1u << kFilter2Log2);
+        return est;
+    };
+    uint32_t K = D;
+    double best = 1e30;
+    for (uint32_t k = reqK ? reqK : D; k <= (reqK ? reqK : kcap); k++) {
+        if (t.pack2 && (k == D + 1 || k == D + 2)) continue;  // the exact form's keys
+        const double est = estimate(k);
+        if (est <= best * 1.001) {
+            best = est;
+            K = k;
+        }
+    }
+    // Two-bit symbols: the exact form (the trie's first D + E levels, E = 1 or 2, as a
+    // direct bitmap over (D+E)-symbol keys: one cheap probe per start) when asked for (a
+    // key of D + 1 or D + 2 symbols), and by default when its pass rate (the (D+E)-prefixes
+    // plus every extension of a whole pattern shorter than D + E) is close to the best
+    // hashed filter's. Keys of D + E symbols of each pattern; a pattern of D + e symbols
+    // (e < E) stands for all its 4^(E-e) extensions.
+    auto exact_keys = [&](uint32_t E) {
+        std::vector<uint32_t> keys;
+        for (uint32_t j = 0; j < a->n_pats; j++) {
+            const uint32_t L = a->pat_len[j];
+            if (L >= D + E) {
+                keys.push_back(root_key(P[j], D + E, bits));
+            } else {
+                const uint32_t e = L - D, free = 2 * (E - e);
+                const uint32_t base = root_key(P[j], L, bits) << free;
+                for (uint32_t x = 0; x < (1u << free); x++) keys.push_back(base | x);
+            }
+        }
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        return keys;
+    };
+    uint32_t E = 0;
+    if (t.pack2 && (reqK == D + 1 || reqK == D + 2)) E = reqK - D;
+    if (t.pack2 && reqK == 0) {
+        double e_best = 1e30;
+        for (uint32_t e = 1; e <= 2; e++) {
+            const double est = (double)exact_keys(e).size() / (double)(1ull << (2 * (D + e)));
+            if (est < e_best * 0.999) {
+                e_best = est;
+                E = e;
+            }
+        }
+        if (!(e_best <= std::max(1.25 * best, best + 0.002))) E = 0;
+    }
+    if (E) {
+        const uint32_t K1 = D + E, kbits = 2 * K1;
         const uint32_t fwords = std::max<uint32_t>(4, (1u << kbits) / 32);  // whole 16-byte units
         t.filter_k = K1;
         t.filter_log2 = kbits;
@@ -93,16 +154,8 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
         for (uint32_t j = 0; j < a->n_pats; j++) {
             const uint32_t key = root_key(P[j], D, bits);
             root[key >> 5] |= 1u << (key & 31);
-            if (a->pat_len[j] > D) {
-                const uint32_t k1 = root_key(P[j], K1, bits);
-                img[k1 >> 5] |= 1u << (k1 & 31);
-            } else {  // a whole pattern of D symbols: every next symbol passes
-                for (uint32_t x = 0; x < 4; x++) {
-                    const uint32_t k1 = (key << 2) | x;
-                    img[k1 >> 5] |= 1u << (k1 & 31);
-                }
-            }
         }
+        for (uint32_t k1 : exact_keys(E)) img[k1 >> 5] |= 1u << (k1 & 31);
         uint16_t *rank = reinterpret_cast<uint16_t *>(img + t.rank_word);
         uint32_t run = 0;
         for (uint32_t w = 0; w < root_words; w++) {
@@ -113,26 +166,6 @@ void build_lds_image(pfac_automaton *a, const std::vector<const uint8_t *> &P, u
         return;
     }
     t.exact = 0;
-    uint32_t K = D;
-    double best = 1e30;
-    for (uint32_t k = reqK ? reqK : D; k <= (reqK ? reqK : kcap); k++) {
-        std::vector<uint32_t> sk, lk;
-        for (uint32_t j = 0; j < a->n_pats; j++) {
-            if (a->pat_len[j] < k) sk.push_back(root_key(P[j], D, bits));
-            else lk.push_back(filter_key(P[j], k, t.pack2));
-        }
-        std::sort(sk.begin(), sk.end());
-        sk.erase(std::unique(sk.begin(), sk.end()), sk.end());
-        std::sort(lk.begin(), lk.end());
-        lk.erase(std::unique(lk.begin(), lk.end()), lk.end());
-        const double space = std::pow((double)a->alphabet, (double)k);
-        double est = (double)sk.size() / root_nbits + (double)lk.size() / space;
-        if (k > D) est += (double)lk.size() / (double)(1u << kMaxFilterLog2) * (double)lk.size() / (double)(1u << kFilter2Log2);
-        if (est <= best * 1.001) {
-            best = est;
-            K = k;
-        }
-    }
     uint32_t flog2 = 0;
     std::vector<uint32_t> fkeys;
     bool any_short = false;
@@ -256,7 +289,86 @@ void finish_automaton(pfac_automaton *a) {
         if (a->out_first[q + 1] > a->out_first[q]) a->n_term++;
     build_tails(a);    // over the trie
     build_records(a);  // the walked table; tails move onto its records
-    const uint32_t R = a->n_rec;
+    // The device table. The compressed table (Section 3.2) is its records as they are,
+    // with a path tail per record. The plain table collapses every unary tail: a node
+    // below the root image's deepest possible level whose subtree is one path ending at
+    // its only terminal (a tail head) keeps its own word, with the tail flag set and the
+    // index of its tail record in place of the first child; the nodes of the path below
+    // it are not stored. Nodes down to that level are all kept, so they keep their
+    // breadth-first indices (the root image depends on them).
+    std::vector<uint32_t> dfirst, dord;  // device first child (or tail index), node of each device record
+    std::vector<uint8_t> dtail;
+    a->dev_out_first.clear();
+    a->dev_out_ids.clear();
+    if (a->merge_levels) {
+        const uint32_t R = a->n_rec;
+        dfirst = a->rec_first;
+        dtail.assign(R, 0);
+        dord.resize(R);
+        for (uint32_t x = 0; x < R; x++) dord[x] = x;
+        a->dev_out_first = a->rank_first;
+        a->dev_out_ids = a->rank_ids;
+    } else {
+        const uint32_t Q = a->n_nodes;
+        const uint32_t dkeep = a->n_pats ? std::min(a->min_len, a->alphabet <= 4 ? 8u : 2u) : 0u;
+        std::vector<uint32_t> depth(Q, 0), parent(Q, 0);
+        for (uint32_t d = 0; d + 1 < a->depth_start.size(); d++)
+            for (uint32_t q = a->depth_start[d]; q < a->depth_start[d + 1] && q < Q; q++) depth[q] = d;
+        auto deg = [&](uint32_t q) {
+            uint32_t c = 0;
+            for (uint32_t w = 0; w < a->nbw; w++) c += popc64(a->bitmap[(size_t)q * a->nbw + w]);
+            return c;
+        };
+        for (uint32_t q = 0; q < Q; q++)
+            for (uint32_t i = 0, k = deg(q); i < k; i++) parent[a->first_child[q] + i] = q;
+        auto tailed = [&](uint32_t q) { return a->dev_tails[(size_t)q * 4 + 1] != 0 && depth[q] >= dkeep; };
+        std::vector<uint8_t> head(Q, 0), below(Q, 0);  // below: inside a head's path
+        std::vector<uint32_t> nid(Q, 0);
+        std::vector<uint32_t> heads;
+        for (uint32_t q = 0; q < Q; q++) {
+            if (q > 0) below[q] = head[parent[q]] || below[parent[q]];
+            if (below[q]) continue;
+            head[q] = tailed(q) && !(q > 0 && tailed(parent[q]));
+            nid[q] = (uint32_t)dord.size();
+            dord.push_back(q);
+            if (head[q]) heads.push_back(q);
+        }
+        const uint32_t R = (uint32_t)dord.size();
+        dfirst.assign(R, 0);
+        dtail.assign(R, 0);
+        std::vector<uint32_t> tidx(Q, 0);
+        for (uint32_t i = 0; i < heads.size(); i++) tidx[heads[i]] = i;
+        a->dev_out_first.assign(R + 1, 0);
+        for (uint32_t x = 0; x < R; x++) {
+            const uint32_t q = dord[x];
+            if (head[q]) {
+                dtail[x] = 1;
+                dfirst[x] = tidx[q];
+            } else {
+                dfirst[x] = deg(q) ? nid[a->first_child[q]] : 0u;
+            }
+            a->dev_out_ids.insert(a->dev_out_ids.end(), a->out_ids.begin() + a->out_first[q],
+                                  a->out_ids.begin() + a->out_first[q + 1]);
+            a->dev_out_first[x + 1] = (uint32_t)a->dev_out_ids.size();
+        }
+        // tail records {offset of the path's symbols in the pattern bytes, length, ids of
+        // its end: first index and count in the device id list}
+        std::vector<uint32_t> tails((size_t)heads.size() * 4, 0);
+        for (uint32_t i = 0; i < heads.size(); i++) {
+            const uint32_t *tq = &a->dev_tails[(size_t)heads[i] * 4];
+            const uint32_t leaf = tq[2];
+            tails[(size_t)i * 4 + 0] = tq[0];
+            tails[(size_t)i * 4 + 1] = tq[1];
+            tails[(size_t)i * 4 + 2] = (uint32_t)a->dev_out_ids.size();
+            a->dev_out_ids.insert(a->dev_out_ids.end(), a->out_ids.begin() + a->out_first[leaf],
+                                  a->out_ids.begin() + a->out_first[leaf + 1]);
+            tails[(size_t)i * 4 + 3] = (uint32_t)a->dev_out_ids.size() - tails[(size_t)i * 4 + 2];
+        }
+        a->dev_tails.swap(tails);
+    }
+    const uint32_t R = (uint32_t)dord.size();
+    a->dev_records = R;
+    auto rec_of = [&](uint32_t x) { return a->merge_levels ? x : dord[x]; };  // row of rec_* arrays
     a->dev_nodes.clear();
     a->dev_bm.clear();
     if (a->alphabet <= 32) {
@@ -264,9 +376,12 @@ void finish_automaton(pfac_automaton *a) {
         a->nw = 0;
         a->dev_nodes.resize(R);
         for (uint32_t x = 0; x < R; x++) {
-            uint64_t w = a->rec_bitmap[(size_t)x * a->nbw] & 0xffffffffull;
-            w |= (uint64_t)a->rec_first[x] << 32;
-            if (a->rec_term[x]) w |= kTermBit;
+            const uint32_t r = rec_of(x);
+            if (dfirst[x] > kNarrowIndexMask) throw std::length_error("node index");
+            uint64_t w = a->rec_bitmap[(size_t)r * a->nbw] & 0xffffffffull;
+            w |= (uint64_t)dfirst[x] << 32;
+            if (dtail[x]) w |= kTailBit;
+            if (a->rec_term[r]) w |= kTermBit;
             a->dev_nodes[x] = w;
         }
     } else {
@@ -275,14 +390,16 @@ void finish_automaton(pfac_automaton *a) {
         a->dev_nodes.resize(R);
         a->dev_bm.assign((size_t)R * a->nw, 0);
         for (uint32_t x = 0; x < R; x++) {
-            const uint64_t *b = &a->rec_bitmap[(size_t)x * a->nbw];
+            const uint32_t r = rec_of(x);
+            const uint64_t *b = &a->rec_bitmap[(size_t)r * a->nbw];
             uint64_t r1 = 0, r2 = 0, r3 = 0;
             for (uint32_t w = 0; w < a->nbw; w++) a->dev_bm[(size_t)x * a->nw + w] = b[w];
             if (a->nbw > 1) r1 = popc64(b[0]);
             if (a->nbw > 2) r2 = r1 + popc64(b[1]);
             if (a->nbw > 3) r3 = r2 + popc64(b[2]);
-            uint64_t m = a->rec_first[x] | (r1 << 32) | (r2 << 40) | (r3 << 48);
-            if (a->rec_term[x]) m |= kTermBit;
+            uint64_t m = dfirst[x] | (r1 << 32) | (r2 << 40) | (r3 << 48);
+            if (dtail[x]) m |= kTailBit;
+            if (a->rec_term[r]) m |= kTermBit;
             a->dev_nodes[x] = m;
         }
     }
@@ -391,6 +508,9 @@ int build_automaton_ex(const uint8_t *const *pats, const uint64_t *lens, uint32_
     } catch (const std::bad_alloc &) {
         delete a;
         return PFAC_ENOMEM;
+    } catch (const std::length_error &) {  // a device index past its field
+        delete a;
+        return PFAC_ETOO_LARGE;
     }
     *out = a;
     return PFAC_OK;

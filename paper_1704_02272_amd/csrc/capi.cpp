@@ -83,11 +83,9 @@ extern "C" void pfac_destroy(pfac_automaton *a) { delete a; }
 // Every byte a device copy of the automaton holds in HBM (as the runtime uploads it).
 static uint64_t device_bytes(const pfac_automaton *a) {
     uint64_t b = a->dev_nodes.size() * 8 + a->dev_bm.size() * 8 + a->dev_tails.size() * 4 +
-                 a->pat_bytes.size() + a->lds_image.size() * 4;
-    if (a->merge_levels)
-        b += a->rec_rank.size() * 4 + a->rank_first.size() * 4 + a->rank_ids.size() * 4;
-    else
-        b += a->out_first.size() * 4 + a->out_ids.size() * 4;
+                 a->pat_bytes.size() + a->lds_image.size() * 4 + a->dev_out_first.size() * 4 +
+                 a->dev_out_ids.size() * 4;
+    if (a->merge_levels) b += a->rec_rank.size() * 4;
     return b;
 }
 
@@ -115,6 +113,8 @@ extern "C" int pfac_table_info(const pfac_automaton *a, pfac_table_info_t *o) {
     o->reduced_paper_bytes = (uint64_t)a->reduced_nodes * node_bytes;
     o->node_array_bytes = a->dev_nodes.size() * 8 + a->dev_bm.size() * 8;
     o->stream_scratch = pfac::workspace_count(const_cast<pfac_automaton *>(a));
+    o->device_records = a->dev_records;
+    o->device_tails = a->merge_levels ? 0u : (uint32_t)(a->dev_tails.size() / 4);
     return PFAC_OK;
 }
 

@@ -28,5 +28,8 @@ int launch_set_u64(uint64_t *dst, uint64_t value, hipStream_t s);
 void release_stream(pfac_automaton *a, void *stream);
 // Number of per-stream scratch areas the automaton holds (all devices).
 size_t workspace_count(pfac_automaton *a);
+// Upload the table to the current device if needed and size `stream`'s scratch for
+// scans of up to n bytes, so later scans of that size allocate nothing.
+int reserve_stream(pfac_automaton *a, void *stream, uint64_t n);
 
 }  // namespace pfac

@@ -21,14 +21,15 @@ namespace {
 constexpr int kPlainThreads = 256;
 constexpr int kPlainRows = 16;  // positions per block = 256 * 16
 
-// Child of q on symbol c, or -1 when the bit for c is clear (Eq. 1).
+// Child of q on symbol c, or -1 when the bit for c is clear (Eq. 1); term: whether the
+// child is terminal.
 template <int LAYOUT>
 __device__ __forceinline__ int64_t step(const DevTable &t, uint32_t q, uint32_t c, bool &term) {
     if (LAYOUT == LAYOUT_NARROW) {
         uint64_t w = t.nodes[q];
         uint32_t bm = (uint32_t)w;
         if (!((bm >> c) & 1u)) return -1;
-        uint32_t child = (uint32_t)(w >> 32) & 0x7fffffffu;
+        uint32_t child = (uint32_t)(w >> 32) & kNarrowIndexMask;
         child += __builtin_popcount(bm & ((1u << c) - 1u));
         term = (t.nodes[child] >> 63) != 0;
         return child;
@@ -45,11 +46,31 @@ __device__ __forceinline__ int64_t step(const DevTable &t, uint32_t q, uint32_t 
     }
 }
 
+// The plain table stores a unary path below a tail head as one record (its nodes are
+// not stored); the walk here still takes it one symbol per step: the number of path
+// symbols text[p ..] matches, and its record.
+__device__ __forceinline__ uint4 tail_of(const DevTable &t, uint64_t w, int layout) {
+    const uint32_t x = layout == LAYOUT_NARROW ? (uint32_t)(w >> 32) & kNarrowIndexMask : (uint32_t)w;
+    return reinterpret_cast<const uint4 *>(t.tails)[x];
+}
+__device__ __forceinline__ uint32_t tail_match(const DevTable &t, uint4 tr, const uint8_t *text, uint64_t p,
+                                               uint64_t end) {
+    uint32_t k = 0;
+    while (k < tr.y && p + k < end && text[p + k] == t.tail_bytes[tr.x + k]) k++;
+    return k;
+}
+
 // Number of pattern ids on the walk from start s (every terminal the walk passes).
 template <int LAYOUT>
 __device__ uint32_t count_at(const DevTable &t, const uint8_t *text, uint64_t s, uint64_t end) {
     uint32_t q = 0, cnt = 0;
     for (uint64_t p = s; p < end; p++) {
+        const uint64_t w = t.nodes[q];
+        if (w & kTailBit) {
+            const uint4 tr = tail_of(t, w, LAYOUT);
+            if (tail_match(t, tr, text, p, end) == tr.y) cnt += tr.w;
+            break;
+        }
         uint32_t c = text[p];
         if (c >= t.alphabet) break;
         bool term = false;
@@ -69,6 +90,15 @@ __device__ void emit_at(const DevTable &t, const uint8_t *text, uint64_t s, uint
     uint32_t q = 0, k = 0, nterm = 0;
     const uint64_t hi = s << 32;
     for (uint64_t p = s; p < end && k < cnt; p++) {
+        const uint64_t w = t.nodes[q];
+        if (w & kTailBit) {
+            const uint4 tr = tail_of(t, w, LAYOUT);
+            if (tail_match(t, tr, text, p, end) == tr.y) {
+                nterm++;
+                for (uint32_t i = tr.z; i < tr.z + tr.w; i++) keys[o + k++] = hi | t.out_ids[i];
+            }
+            break;
+        }
         uint32_t c = text[p];
         if (c >= t.alphabet) break;
         bool term = false;
@@ -198,6 +228,13 @@ __global__ __launch_bounds__(kPlainThreads) void prefix_hist(DevTable t, const u
     for (uint64_t s = (uint64_t)blockIdx.x * kPlainThreads + threadIdx.x; s < n; s += stride) {
         uint32_t q = 0, d = 0;
         for (uint64_t p = s; p < n && d < cap; p++) {
+            const uint64_t w = t.nodes[q];
+            if (w & kTailBit) {  // the rest of a unary path, symbol by symbol
+                const uint4 tr = tail_of(t, w, LAYOUT);
+                const uint32_t m = tail_match(t, tr, text, p, n);
+                d = d + m < cap ? d + m : cap;
+                break;
+            }
             const uint32_t c = text[p];
             if (c >= t.alphabet) break;
             bool term = false;

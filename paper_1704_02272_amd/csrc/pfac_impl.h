@@ -14,21 +14,27 @@ namespace pfac {
 //
 // NARROW (alphabet <= 32): one 64-bit word per node:
 //     bits  0..31  child bitmap (bit c = symbol c)
-//     bits 32..62  first-child index (0 when the node has no child)
+//     bits 32..61  first-child index (0 when the node has no child), or the tail index
+//     bit  62      tail flag (plain table only)
 //     bit  63      terminal: at least one pattern ends here
 //   This is the paper's 8-byte node at |Sigma| = 32 (Section 3.1) with the terminal flag
 //   taken from the top bit of the offset.
 //
 // WIDE (alphabet 33..256): bitmap words and per-node metadata in two arrays:
 //     bm[q * NW + w]  bits 64w .. 64w+63 of the child bitmap, NW = 1, 2 or 4
-//     meta[q]         bits  0..31 first-child index
+//     meta[q]         bits  0..31 first-child index, or the tail index
 //                     bits 32..55 three rank bytes: set bits in words < 1, < 2, < 3
+//                     bit  62     tail flag (plain table only)
 //                     bit  63     terminal
 //   A lookup reads one bitmap word and the metadata word; Eq. 1's popcount then covers
 //   one 64-bit word plus a stored rank byte instead of up to four words.
 enum Layout : uint32_t { LAYOUT_NARROW = 0, LAYOUT_WIDE = 1 };
 
 constexpr uint64_t kTermBit = 1ull << 63;
+// Tail flag (plain table): the node heads a collapsed unary path; its first-child field
+// holds the index of the path's tail record instead (see DevTable::tails).
+constexpr uint64_t kTailBit = 1ull << 62;
+constexpr uint32_t kNarrowIndexMask = 0x3fffffffu;  // NARROW: first child / tail index, bits 32..61
 constexpr uint32_t kMaxPatternLen = 1u << 24;
 constexpr uint32_t kMaxNodes = 0x7fffffffu;
 constexpr uint32_t kMaxMergeLevels = 255;  // levels >= the deepest height merge everything
@@ -49,10 +55,13 @@ struct DevTable {
     const uint32_t *out_first;  // n_nodes + 1: ids of q at out_ids[out_first[q] .. [q+1])
     const uint32_t *out_ids;
     const uint32_t *lds_image;  // see above
-    // Path tails: tails[4q .. 4q+3] = {byte offset in tail_bytes, length, end node, 0}
-    // when everything below q is one path whose only terminal is its end (length > 0),
-    // else zeros. A walk at such a node compares the text with the path's symbols at
-    // once instead of stepping node by node; the result is the same.
+    // Path tails. Compressed table: tails[4q .. 4q+3] = {byte offset in tail_bytes,
+    // length, end record, 0} when everything below record q is one path whose only
+    // terminal is its end (length > 0), else zeros; a walk at such a record compares the
+    // text with the path's symbols at once instead of stepping record by record. Plain
+    // table: one record per tail head (a node with the tail flag; index in its word):
+    // {byte offset of the path's symbols, length, first index and count of the end's
+    // ids in out_ids}; the path's nodes are not stored.
     const uint32_t *tails;
     const uint8_t *tail_bytes;
     uint32_t alphabet;
@@ -68,8 +77,8 @@ struct DevTable {
     uint32_t has_short;         // 1: some pattern is shorter than k (short bitmap used)
     uint32_t filter_log2;       // log2(bits of the first-probe region); 0 = no filter
     uint32_t sampled;           // 1: sampled prefilter layout (every second start probed)
-    uint32_t exact;             // 1: exact form: the filter is the (D+1)-symbol bitmap (two-bit
-                                //    symbols, filter_k = D + 1)
+    uint32_t exact;             // 1: exact form: the filter is the (D+E)-symbol bitmap (two-bit
+                                //    symbols, filter_k = D + E, E = 1 or 2)
     uint32_t lds_words;         // total image size in 32-bit words
     uint32_t root_word;         // word offset of the root bitmap
     uint32_t rank_word;         // word offset of the rank table
@@ -168,7 +177,9 @@ struct pfac_automaton {
     // Device images.
     std::vector<uint64_t> dev_nodes, dev_bm;
     std::vector<uint32_t> lds_image;
-    std::vector<uint32_t> dev_tails;  // 4 per node, see DevTable::tails
+    std::vector<uint32_t> dev_tails;  // see DevTable::tails
+    std::vector<uint32_t> dev_out_first, dev_out_ids;  // ids as the device table indexes them
+    uint32_t dev_records = 0;         // records of the device table
     pfac::DevTable shape{};  // pointer fields null; filled per device copy
     std::vector<pfac::DeviceCopy *> copies;
     std::mutex mu;

@@ -190,10 +190,10 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
         c->cus = (uint32_t)cus;
     rc = upload_vec(a->dev_nodes, &c->nodes);
     if (!rc && a->layout == LAYOUT_WIDE) rc = upload_vec(a->dev_bm, &c->bm);
-    // ids by node (plain trie), or by rank of the spelled string plus the rank words
-    // (compressed trie)
-    if (!rc) rc = upload_vec(a->merge_levels ? a->rank_first : a->out_first, &c->out_first);
-    if (!rc) rc = upload_vec(a->merge_levels ? a->rank_ids : a->out_ids, &c->out_ids);
+    // ids by device record and tail (plain table), or by rank of the spelled string plus
+    // the rank words (compressed table)
+    if (!rc) rc = upload_vec(a->dev_out_first, &c->out_first);
+    if (!rc) rc = upload_vec(a->dev_out_ids, &c->out_ids);
     if (!rc && a->merge_levels) rc = upload_vec(a->rec_rank, &c->rk);
     if (!rc) rc = upload_vec(a->lds_image, &c->lds_image);
     if (!rc) rc = upload_vec(a->dev_tails, &c->tails);
@@ -314,6 +314,19 @@ static int ensure_tiles(Workspace *w, uint64_t n, uint32_t span_log2, void *stre
     return PFAC_OK;
 }
 
+}  // namespace pfac
+
+namespace pfac {
+int reserve_stream(pfac_automaton *a, void *stream, uint64_t n) {
+    if (!a || n >= (1ull << 32)) return PFAC_EINVAL;
+    std::lock_guard<std::mutex> g(a->mu);
+    DeviceCopy *c = nullptr;
+    int rc = get_copy(a, &c);
+    if (rc) return rc;
+    const uint32_t span_log2 = a->span_log2 ? a->span_log2 : auto_span_log2(n, (uint64_t)c->cus * kWaves);
+    Workspace *w = nullptr;
+    return get_workspace(c, stream, n, PFAC_ALGO_TILED, span_log2, &w);
+}
 }  // namespace pfac
 
 // Enqueue one scan of a text (offsets == null) or a packet batch.

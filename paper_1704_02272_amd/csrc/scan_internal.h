@@ -63,10 +63,11 @@ static_assert((1u << kStepLog2) == kStep, "step length is a power of two");
 //   sampled   [second-probe part: 2^16 bits][first-probe part: 2^17 bits][3-gram part: 2^19 bits]
 //             [root bitmap][rank table][step staging, 576 words a wave]
 //             [survivor queues, 512 entries a wave]
-//   exact     [(D+1)-symbol bitmap: up to 2^18 bits][root bitmap][rank table]
+//   exact     [(D+E)-symbol bitmap: up to 2^20 bits][root bitmap][rank table]
 //             [survivor queues, 512 entries a wave]
 //             two-bit symbols: every start probed once in an exact bitmap of the trie's
-//             first D+1 levels (no hash, no false positive beyond the truncation)
+//             first D+E levels, E = 1 or 2 (no hash, no false positive beyond the
+//             truncation)
 //             patterns of four or more bytes and k = 4: only every second start is
 //             probed, with the 3-gram there against the 3-grams at offsets 0 and 1 of
 //             every pattern; the two starts it stands for are then checked against the
@@ -120,11 +121,11 @@ struct Lds<kFormSampled> {
     static constexpr uint32_t queues = stage + kWaves * kStageWords;
     static constexpr uint32_t words = queues + kWaves * qcap / 2;
 };
-// Exact form (two-bit symbols): the trie truncated one level below the root image, as a
-// direct bitmap over (D+1)-symbol keys: a key's bit is set when some pattern begins with
-// it, or when its first D symbols are a whole pattern (every extension of a pattern of
-// length D is set). 4^(D+1) bits, at most 2^18 (32 KiB, D = 8).
-constexpr uint32_t kExactWordsMax = 1u << 13;
+// Exact form (two-bit symbols): the trie truncated E = 1 or 2 levels below the root image,
+// as a direct bitmap over (D+E)-symbol keys: a key's bit is set when some pattern begins
+// with it, or when a prefix of it is a whole pattern (every extension of a pattern shorter
+// than D + E is set). 4^(D+E) bits, at most 2^20 (128 KiB, D = 8, E = 2).
+constexpr uint32_t kExactWordsMax = 1u << 15;
 template <>
 struct Lds<kFormExact> {
     static constexpr uint32_t root = kExactWordsMax;

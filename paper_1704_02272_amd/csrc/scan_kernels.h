@@ -148,7 +148,7 @@ struct Trie {
             const uint64_t w = t.nodes[q];
             const uint32_t bm = (uint32_t)w;
             if (!((bm >> c) & 1u)) return -1;
-            return (int64_t)(((uint32_t)(w >> 32) & 0x7fffffffu) + __builtin_popcount(bm & ((1u << c) - 1u)));
+            return (int64_t)(((uint32_t)(w >> 32) & kNarrowIndexMask) + __builtin_popcount(bm & ((1u << c) - 1u)));
         } else {
             const uint32_t wi = c >> 6, b = c & 63;
             const uint64_t word = t.bm[((size_t)q << t.nw_log2) + wi];
@@ -160,7 +160,34 @@ struct Trie {
         }
     }
 
-    // Path tail of q: x = offset in tail_bytes, y = length (0: none), z = end node.
+    // Plain table: the node word's tail flag, its first-child (or tail) index, and the
+    // child of q on c from its word w already loaded (Eq. 1), or -1.
+    __device__ __forceinline__ static bool w_tail(uint64_t w) { return (w & kTailBit) != 0; }
+    __device__ __forceinline__ static uint32_t w_index(uint64_t w) {
+        return LAYOUT == LAYOUT_NARROW ? (uint32_t)(w >> 32) & kNarrowIndexMask : (uint32_t)w;
+    }
+    __device__ __forceinline__ int64_t child_w(uint32_t q, uint64_t w, uint32_t c) const {
+        if (c >= t.alphabet) return -1;
+        if (LAYOUT == LAYOUT_NARROW) {
+            const uint32_t bm = (uint32_t)w;
+            if (!((bm >> c) & 1u)) return -1;
+            return (int64_t)(w_index(w) + __builtin_popcount(bm & ((1u << c) - 1u)));
+        } else {
+            const uint32_t wi = c >> 6, b = c & 63;
+            const uint64_t word = t.bm[((size_t)q << t.nw_log2) + wi];
+            if (!((word >> b) & 1ull)) return -1;
+            uint32_t r = (uint32_t)w;
+            if (wi) r += (uint32_t)(w >> (24 + 8 * wi)) & 0xffu;
+            return (int64_t)(r + __builtin_popcountll(word & ((1ull << b) - 1ull)));
+        }
+    }
+    // Plain table: tail record {offset in tail_bytes, length, first id index, id count}.
+    __device__ __forceinline__ uint4 tail_rec(uint64_t w) const {
+        return reinterpret_cast<const uint4 *>(t.tails)[w_index(w)];
+    }
+
+    // Compressed table: path tail of q: x = offset in tail_bytes, y = length (0: none),
+    // z = end record.
     __device__ __forceinline__ uint4 tail(uint32_t q) const { return reinterpret_cast<const uint4 *>(t.tails)[q]; }
 
     // Whether text[i .. i+len) spells tail_bytes[off .. off+len). Both runs are read as
@@ -229,6 +256,40 @@ struct Trie {
     // (q: the root, or for a compressed table a record below shared_base.)
     __device__ WalkResult walk_from(uint32_t q, const uint8_t *__restrict__ text, uint64_t i, uint64_t end) const {
         WalkResult r{0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (!MERGED) {
+            // plain table: one node word per step; a tail head ends the walk with one
+            // comparison of the rest of its path
+            for (;;) {
+                const uint64_t w = t.nodes[q];
+                if (w & kTermBit) {
+                    const uint32_t f = t.out_first[q], k = t.out_first[q + 1] - f;
+                    r.cnt += k;
+                    if (r.nterm == 0) {
+                        r.f0 = f;
+                        r.k0 = k;
+                    }
+                    r.nterm++;
+                }
+                if (i >= end) break;
+                if (w_tail(w)) {
+                    const uint4 tr = tail_rec(w);
+                    if (i + tr.y <= end && tail_equal(text, i, tr.x, tr.y)) {
+                        r.cnt += tr.w;
+                        if (r.nterm == 0) {
+                            r.f0 = tr.z;
+                            r.k0 = tr.w;
+                        }
+                        r.nterm++;
+                    }
+                    break;
+                }
+                const int64_t nq = child_w(q, w, text[i]);
+                if (nq < 0) break;
+                q = (uint32_t)nq;
+                i++;
+            }
+            return r;
+        }
         RankState rs{q, 0};
         for (;;) {
             const uint4 tl = tail(q);
@@ -258,6 +319,29 @@ struct Trie {
         uint32_t k = 0, nterm = 0;
         uint64_t i = i0 == ~0ull ? s : i0;
         RankState rs{q, 0};
+        if constexpr (!MERGED) {
+            for (;;) {
+                const uint64_t w = t.nodes[q];
+                if (w & kTermBit) {
+                    nterm++;
+                    for (uint32_t x = t.out_first[q]; x < t.out_first[q + 1]; x++) keys[o + k++] = hi | t.out_ids[x];
+                    if (k >= cnt) break;
+                }
+                if (i >= end) break;
+                if (w_tail(w)) {
+                    const uint4 tr = tail_rec(w);
+                    if (i + tr.y <= end && tail_equal(text, i, tr.x, tr.y)) {
+                        nterm++;
+                        for (uint32_t x = tr.z; x < tr.z + tr.w; x++) keys[o + k++] = hi | t.out_ids[x];
+                    }
+                    break;
+                }
+                const int64_t nq = child_w(q, w, text[i]);
+                if (nq < 0) break;
+                q = (uint32_t)nq;
+                i++;
+            }
+        } else
         for (;;) {
             const uint4 tl = tail(q);
             const bool tq = is_term(q);
@@ -316,6 +400,45 @@ struct RootWalk {
         WalkResult r{0, 0, 0, 0, 0, 0, 0, 0, 0};
         RankState rs{q, 0};  // the depth-D records lie below shared_base
         uint64_t i = s + D;
+        if constexpr (!MERGED) {
+            // plain table: one node word per step; a tail head ends the walk with one
+            // comparison of the rest of its path (its end is not a node: q0 = kNone)
+            auto note = [&](uint32_t f, uint32_t k, uint32_t qn, uint32_t depth) {
+                r.cnt += k;
+                if (r.nterm == 0) {
+                    r.f0 = f;
+                    r.k0 = k;
+                    r.id0 = t.out_ids[f];  // used only when k == 1
+                    r.q0 = qn;
+                    r.d0 = depth;
+                } else if (r.nterm == 1) {
+                    r.k1 = k;
+                    r.id1 = t.out_ids[f];
+                }
+                r.nterm++;
+            };
+            for (;;) {
+                const uint64_t w = t.nodes[q];
+                if (w & kTermBit) {
+                    const uint32_t f = t.out_first[q];
+                    note(f, t.out_first[q + 1] - f, q, (uint32_t)(i - s));
+                }
+                if (i >= end) break;
+                if (T.w_tail(w)) {
+                    const uint4 tr = T.tail_rec(w);
+                    if (i + tr.y <= end && T.tail_equal(text, i, tr.x, tr.y))
+                        note(tr.z, tr.w, kNone, (uint32_t)(i - s) + tr.y);
+                    break;
+                }
+                const uint32_t d = (uint32_t)(i - s);
+                const uint32_t c = d < 8 ? (uint32_t)(w8 >> (8 * d)) & 0xffu : (uint32_t)text[i];
+                const int64_t nq = T.child_w(q, w, c);
+                if (nq < 0) break;
+                q = (uint32_t)nq;
+                i++;
+            }
+            return r;
+        }
         for (;;) {
             const uint4 tl = T.tail(q);
             const bool tq = T.is_term(q);

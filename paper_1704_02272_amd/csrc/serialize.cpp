@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <new>
+#include <stdexcept>
 #include <vector>
 
 #include "pfac.h"
@@ -284,6 +285,9 @@ extern "C" int pfac_load(const uint8_t *buf, uint64_t size, pfac_automaton **out
     } catch (const std::bad_alloc &) {
         delete a;
         return PFAC_ENOMEM;
+    } catch (const std::length_error &) {
+        delete a;
+        return PFAC_EFORMAT;
     } catch (int) {
         delete a;
         return PFAC_EFORMAT;

@@ -121,6 +121,8 @@ int alloc_slot(pfac_server *sv, Slot &s) {
     if (hipHostMalloc(&s.h_keys, c.key_capacity * 8, hipHostMallocDefault) != hipSuccess) return PFAC_ENOMEM;
     if (hipHostMalloc(&s.h_count, 8, hipHostMallocDefault) != hipSuccess) return PFAC_ENOMEM;
     s.cap = c.key_capacity;
+    if (c.flags & PFAC_SERVER_EAGER)  // scratch for a full batch now, so launches never allocate
+        return pfac::reserve_stream(sv->a, s.s, c.max_batch_bytes);
     return pfac_graph_create(sv->a, s.d_bytes, s.d_offs, c.max_batch_bytes, c.max_batch_packets, s.d_keys, s.cap,
                              s.d_count, s.d_sizes, s.s, &s.g);
 }
@@ -154,8 +156,9 @@ void take_requests(pfac_server *sv, Slot &s) {
     }
 }
 
-// Stage the slot's requests as one CSR batch and launch its graph. Called without mu.
-int launch_slot(Slot &s) {
+// Stage the slot's requests as one CSR batch and launch its scan (a replay of the slot's
+// graph, or an eager launch pair). Called without mu.
+int launch_slot(pfac_server *sv, Slot &s) {
     s.byte0.clear();
     uint64_t nb = 0;
     uint32_t np = 0;
@@ -174,8 +177,13 @@ int launch_slot(Slot &s) {
     if (nb && hipMemcpyAsync(s.d_bytes, s.h_bytes, nb, hipMemcpyHostToDevice, s.s) != hipSuccess) return PFAC_EHIP;
     if (hipMemcpyAsync(s.d_offs, s.h_offs, ((uint64_t)np + 1) * 8, hipMemcpyHostToDevice, s.s) != hipSuccess)
         return PFAC_EHIP;
-    if (hipMemcpyAsync(s.d_sizes, s.h_sizes, 16, hipMemcpyHostToDevice, s.s) != hipSuccess) return PFAC_EHIP;
-    int rc = pfac_graph_launch(s.g, s.s);
+    int rc;
+    if (s.g) {
+        if (hipMemcpyAsync(s.d_sizes, s.h_sizes, 16, hipMemcpyHostToDevice, s.s) != hipSuccess) return PFAC_EHIP;
+        rc = pfac_graph_launch(s.g, s.s);
+    } else {
+        rc = pfac_scan_batch_async(sv->a, s.d_bytes, s.d_offs, np, nb, s.d_keys, s.cap, s.d_count, s.s);
+    }
     if (rc) return rc;
     if (hipMemcpyAsync(s.h_count, s.d_count, 8, hipMemcpyDeviceToHost, s.s) != hipSuccess) return PFAC_EHIP;
     if (hipEventRecord(s.done, s.s) != hipSuccess) return PFAC_EHIP;
@@ -294,7 +302,7 @@ void worker_main(pfac_server *sv) {
             s.busy = true;
             sv->st_batches++;
             lk.unlock();
-            const int rc = launch_slot(s);
+            const int rc = launch_slot(sv, s);
             lk.lock();
             progressed = true;
             if (rc) {

@@ -51,7 +51,7 @@ class TableInfo(C.Structure):
                                   "lds_image_bytes", "merge_levels", "reduced_nodes",
                                   "table_records", "shared_base")] + [
         ("reduced_paper_bytes", C.c_uint64), ("node_array_bytes", C.c_uint64),
-        ("stream_scratch", C.c_uint64)]
+        ("stream_scratch", C.c_uint64), ("device_records", C.c_uint32), ("device_tails", C.c_uint32)]
 
 
 class BuildOptions(C.Structure):
@@ -69,7 +69,7 @@ class Matches(C.Structure):
 class ServerConfig(C.Structure):
     _fields_ = [("slots", C.c_uint32), ("max_batch_packets", C.c_uint32), ("max_batch_bytes", C.c_uint64),
                 ("key_capacity", C.c_uint64), ("max_pending_bytes", C.c_uint64),
-                ("device_memory_budget", C.c_uint64), ("reserved", C.c_uint32 * 4)]
+                ("device_memory_budget", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 class Result(C.Structure):
@@ -89,6 +89,7 @@ class ServerStats(C.Structure):
 MATCH_DTYPE = np.dtype([("start", np.uint64), ("pattern_id", np.uint32), ("reserved", np.uint32)])
 
 PFAC_ALGO_AUTO, PFAC_ALGO_PLAIN, PFAC_ALGO_TILED = 0, 1, 2
+PFAC_SERVER_EAGER = 1
 ALGOS = {"auto": PFAC_ALGO_AUTO, "plain": PFAC_ALGO_PLAIN, "tiled": PFAC_ALGO_TILED}
 
 

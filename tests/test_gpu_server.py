@@ -34,11 +34,13 @@ def drain(srv, tickets, timeout_s=60.0):
     return got
 
 
-def test_alone_equals_in_mix_equals_oracle(served):
+@pytest.mark.parametrize("flags", [0, pfac.PFAC_SERVER_EAGER])
+def test_alone_equals_in_mix_equals_oracle(served, flags):
     w, want = served
     torch.cuda.set_device(0)
     a = pfac.pfac_build(w.patterns, w.alphabet)
-    srv = pfac.pfac_server_create(a, slots=3, max_batch_bytes=1 << 20)
+    srv = pfac.pfac_server_create(a, slots=3, max_batch_bytes=1 << 20, flags=flags)
+    assert srv.config()["flags"] == flags
     assert srv.config()["slots"] == 3
     probe = 7
     t = srv.submit(w.requests[probe].data, w.requests[probe].offsets)
