@@ -352,7 +352,8 @@ void finish_automaton(pfac_automaton *a) {
             a->dev_out_first[x + 1] = (uint32_t)a->dev_out_ids.size();
         }
         // tail records {offset of the path's symbols in the pattern bytes, length, ids of
-        // its end: first index and count in the device id list}
+        // its end: first index in the device id list (the id itself when it is the only
+        // one), count}
         std::vector<uint32_t> tails((size_t)heads.size() * 4, 0);
         for (uint32_t i = 0; i < heads.size(); i++) {
             const uint32_t *tq = &a->dev_tails[(size_t)heads[i] * 4];
@@ -363,6 +364,7 @@ void finish_automaton(pfac_automaton *a) {
             a->dev_out_ids.insert(a->dev_out_ids.end(), a->out_ids.begin() + a->out_first[leaf],
                                   a->out_ids.begin() + a->out_first[leaf + 1]);
             tails[(size_t)i * 4 + 3] = (uint32_t)a->dev_out_ids.size() - tails[(size_t)i * 4 + 2];
+            if (tails[(size_t)i * 4 + 3] == 1) tails[(size_t)i * 4 + 2] = a->dev_out_ids.back();  // the id itself
         }
         a->dev_tails.swap(tails);
     }
@@ -375,13 +377,21 @@ void finish_automaton(pfac_automaton *a) {
         a->layout = LAYOUT_NARROW;
         a->nw = 0;
         a->dev_nodes.resize(R);
+        // two-bit symbols, plain table: a terminal with one pattern id carries that id in
+        // the bitmap word's spare bits (bit 4 set, id in bits 5..31), so a walk reads it
+        // with the node instead of through the id lists
+        const bool one_id = a->alphabet <= 4 && !a->merge_levels && a->n_pats <= kOneIdMax;
         for (uint32_t x = 0; x < R; x++) {
             const uint32_t r = rec_of(x);
             if (dfirst[x] > kNarrowIndexMask) throw std::length_error("node index");
             uint64_t w = a->rec_bitmap[(size_t)r * a->nbw] & 0xffffffffull;
             w |= (uint64_t)dfirst[x] << 32;
             if (dtail[x]) w |= kTailBit;
-            if (a->rec_term[r]) w |= kTermBit;
+            if (a->rec_term[r]) {
+                w |= kTermBit;
+                if (one_id && a->dev_out_first[x + 1] - a->dev_out_first[x] == 1)
+                    w |= kOneIdBit | ((uint64_t)a->dev_out_ids[a->dev_out_first[x]] << kOneIdShift);
+            }
             a->dev_nodes[x] = w;
         }
     } else {

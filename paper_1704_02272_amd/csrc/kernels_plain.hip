@@ -95,7 +95,9 @@ __device__ void emit_at(const DevTable &t, const uint8_t *text, uint64_t s, uint
             const uint4 tr = tail_of(t, w, LAYOUT);
             if (tail_match(t, tr, text, p, end) == tr.y) {
                 nterm++;
-                for (uint32_t i = tr.z; i < tr.z + tr.w; i++) keys[o + k++] = hi | t.out_ids[i];
+                if (tr.w == 1) keys[o + k++] = hi | tr.z;  // the record holds the id itself
+                else
+                    for (uint32_t i = tr.z; i < tr.z + tr.w; i++) keys[o + k++] = hi | t.out_ids[i];
             }
             break;
         }

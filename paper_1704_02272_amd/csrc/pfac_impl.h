@@ -15,6 +15,7 @@ namespace pfac {
 // NARROW (alphabet <= 32): one 64-bit word per node:
 //     bits  0..31  child bitmap (bit c = symbol c)
 //     bits 32..61  first-child index (0 when the node has no child), or the tail index
+//   (two-bit symbols, plain table: bit 4 flags a terminal with one id, held in bits 5..31)
 //     bit  62      tail flag (plain table only)
 //     bit  63      terminal: at least one pattern ends here
 //   This is the paper's 8-byte node at |Sigma| = 32 (Section 3.1) with the terminal flag
@@ -35,6 +36,11 @@ constexpr uint64_t kTermBit = 1ull << 63;
 // holds the index of the path's tail record instead (see DevTable::tails).
 constexpr uint64_t kTailBit = 1ull << 62;
 constexpr uint32_t kNarrowIndexMask = 0x3fffffffu;  // NARROW: first child / tail index, bits 32..61
+// Two-bit symbols, plain table: the bitmap field holds four bits; a terminal with a single
+// pattern id keeps it in bits 5..31 of the word, flagged by bit 4.
+constexpr uint64_t kOneIdBit = 1ull << 4;
+constexpr uint32_t kOneIdShift = 5;
+constexpr uint32_t kOneIdMax = 1u << 27;
 constexpr uint32_t kMaxPatternLen = 1u << 24;
 constexpr uint32_t kMaxNodes = 0x7fffffffu;
 constexpr uint32_t kMaxMergeLevels = 255;  // levels >= the deepest height merge everything
@@ -60,8 +66,9 @@ struct DevTable {
     // terminal is its end (length > 0), else zeros; a walk at such a record compares the
     // text with the path's symbols at once instead of stepping record by record. Plain
     // table: one record per tail head (a node with the tail flag; index in its word):
-    // {byte offset of the path's symbols, length, first index and count of the end's
-    // ids in out_ids}; the path's nodes are not stored.
+    // {byte offset of the path's symbols, length, first index of the end's ids in
+    // out_ids (the id itself when the count is 1), their count}; the path's nodes are
+    // not stored.
     const uint32_t *tails;
     const uint8_t *tail_bytes;
     uint32_t alphabet;

@@ -186,6 +186,19 @@ struct Trie {
         return reinterpret_cast<const uint4 *>(t.tails)[w_index(w)];
     }
 
+    // Plain table: ids of terminal q (word w): the count, and the first id (one = true:
+    // read from the word) or the index of the ids in out_ids.
+    __device__ __forceinline__ uint32_t term_ids(uint32_t q, uint64_t w, uint32_t &fi, bool &one) const {
+        if (LAYOUT == LAYOUT_NARROW && t.alphabet <= 4 && (w & kOneIdBit)) {
+            fi = (uint32_t)w >> kOneIdShift;
+            one = true;
+            return 1;
+        }
+        fi = t.out_first[q];
+        one = false;
+        return t.out_first[q + 1] - fi;
+    }
+
     // Compressed table: path tail of q: x = offset in tail_bytes, y = length (0: none),
     // z = end record.
     __device__ __forceinline__ uint4 tail(uint32_t q) const { return reinterpret_cast<const uint4 *>(t.tails)[q]; }
@@ -262,7 +275,9 @@ struct Trie {
             for (;;) {
                 const uint64_t w = t.nodes[q];
                 if (w & kTermBit) {
-                    const uint32_t f = t.out_first[q], k = t.out_first[q + 1] - f;
+                    uint32_t f;
+                    bool one;
+                    const uint32_t k = term_ids(q, w, f, one);
                     r.cnt += k;
                     if (r.nterm == 0) {
                         r.f0 = f;
@@ -324,7 +339,12 @@ struct Trie {
                 const uint64_t w = t.nodes[q];
                 if (w & kTermBit) {
                     nterm++;
-                    for (uint32_t x = t.out_first[q]; x < t.out_first[q + 1]; x++) keys[o + k++] = hi | t.out_ids[x];
+                    uint32_t f;
+                    bool one;
+                    const uint32_t kk = term_ids(q, w, f, one);
+                    if (one) keys[o + k++] = hi | f;
+                    else
+                        for (uint32_t x = f; x < f + kk; x++) keys[o + k++] = hi | t.out_ids[x];
                     if (k >= cnt) break;
                 }
                 if (i >= end) break;
@@ -332,7 +352,9 @@ struct Trie {
                     const uint4 tr = tail_rec(w);
                     if (i + tr.y <= end && tail_equal(text, i, tr.x, tr.y)) {
                         nterm++;
-                        for (uint32_t x = tr.z; x < tr.z + tr.w; x++) keys[o + k++] = hi | t.out_ids[x];
+                        if (tr.w == 1) keys[o + k++] = hi | tr.z;  // the id itself
+                        else
+                            for (uint32_t x = tr.z; x < tr.z + tr.w; x++) keys[o + k++] = hi | t.out_ids[x];
                     }
                     break;
                 }
@@ -403,31 +425,34 @@ struct RootWalk {
         if constexpr (!MERGED) {
             // plain table: one node word per step; a tail head ends the walk with one
             // comparison of the rest of its path (its end is not a node: q0 = kNone)
-            auto note = [&](uint32_t f, uint32_t k, uint32_t qn, uint32_t depth) {
+            // f: index of the ids, or (one) the single id itself
+            auto note = [&](uint32_t f, uint32_t k, bool one, uint32_t qn, uint32_t depth) {
                 r.cnt += k;
                 if (r.nterm == 0) {
                     r.f0 = f;
                     r.k0 = k;
-                    r.id0 = t.out_ids[f];  // used only when k == 1
+                    if (k == 1) r.id0 = one ? f : t.out_ids[f];  // used only when k == 1
                     r.q0 = qn;
                     r.d0 = depth;
                 } else if (r.nterm == 1) {
                     r.k1 = k;
-                    r.id1 = t.out_ids[f];
+                    if (k == 1) r.id1 = one ? f : t.out_ids[f];
                 }
                 r.nterm++;
             };
             for (;;) {
                 const uint64_t w = t.nodes[q];
                 if (w & kTermBit) {
-                    const uint32_t f = t.out_first[q];
-                    note(f, t.out_first[q + 1] - f, q, (uint32_t)(i - s));
+                    uint32_t f;
+                    bool one;
+                    const uint32_t k = T.term_ids(q, w, f, one);
+                    note(f, k, one, q, (uint32_t)(i - s));
                 }
                 if (i >= end) break;
                 if (T.w_tail(w)) {
                     const uint4 tr = T.tail_rec(w);
                     if (i + tr.y <= end && T.tail_equal(text, i, tr.x, tr.y))
-                        note(tr.z, tr.w, kNone, (uint32_t)(i - s) + tr.y);
+                        note(tr.z, tr.w, tr.w == 1, kNone, (uint32_t)(i - s) + tr.y);
                     break;
                 }
                 const uint32_t d = (uint32_t)(i - s);
