@@ -402,10 +402,19 @@ struct RootWalk {
     __device__ WalkResult count(uint64_t s, uint64_t end) const {
         const uint32_t D = t.root_depth;
         if (s + D > end) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};
+        // the first eight bytes: three aligned dwords when they lie inside the walk's
+        // bounds (bytes past `end` are read but never used), else byte by byte
         uint64_t w8 = 0;
+        const uint64_t b4 = s & ~3ull;
+        if (b4 + 12 <= end) {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(text + b4);
+            const uint32_t x0 = p[0], x1 = p[1], x2 = p[2], sh = (uint32_t)(s & 3);
+            w8 = ((uint64_t)__builtin_amdgcn_alignbyte(x2, x1, sh) << 32) | __builtin_amdgcn_alignbyte(x1, x0, sh);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 8; i++)
-            if (s + i < end) w8 |= (uint64_t)text[s + i] << (8 * i);
+            for (int i = 0; i < 8; i++)
+                if (s + i < end) w8 |= (uint64_t)text[s + i] << (8 * i);
+        }
         uint32_t key = 0;
         for (uint32_t i = 0; i < D; i++) {
             const uint32_t c = (uint32_t)(w8 >> (8 * i)) & 0xffu;
