@@ -260,7 +260,7 @@ def bench_serving(args):
     w = W.serving_256(duration_s=args.serve_seconds, contiguous=True, plant_every=args.plant_every)
     a = pfac.pfac_build(w.patterns, w.alphabet)
     srv = pfac.pfac_server_create(a, slots=args.slots, max_batch_bytes=args.batch_mib << 20,
-                                  flags=pfac.PFAC_SERVER_EAGER if args.eager else 0)
+                                  flags=0 if args.graph else pfac.PFAC_SERVER_EAGER)
     cfg = srv.config()
     ptrs = [(r.data.ctypes.data, r.offsets.ctypes.data, int(r.offsets[-1])) for r in w.requests]
     arr_ns = [int(r.arrival_s * 1e9) for r in w.requests]
@@ -279,20 +279,38 @@ def bench_serving(args):
     n_verify = min(args.verify, n_total)
     verify_idx = set(np.linspace(0, n_total - 1, n_verify).astype(int).tolist()) if n_verify else set()
     ticket_of = {}
-    kept = {}
-    phases = []  # per request: queueing (launch - arrival), service (done - launch), total
+    got_keys = {}
+    # keys are copied out only for the sampled requests: a ticket is added to
+    # verify_tickets before the registered bound moves past it, and any ticket above the
+    # bound (a result that beat its own registration) is kept too
+    verify_tickets = set()
+    registered = {"max": 0}
+    # per request: queueing (launch - arrival), service (done - launch), total; filled in
+    # place so the drain thread allocates nothing per result
+    phases = np.zeros((n_total, 3), dtype=np.float64)
+
+    def want(t):
+        return t in verify_tickets or t > registered["max"]
 
     def drain():
         while done["n"] < n_total and not stop.is_set():
-            for r in srv.poll(timeout_us=50000, with_keys=bool(verify_idx)):
+            for r in srv.poll(timeout_us=50000, with_keys=bool(verify_idx), keys_for=want):
+                k = done["n"]
+                if k < n_total:
+                    phases[k, 0] = r["launch_ns"] - r["arrival_ns"]
+                    phases[k, 1] = r["done_ns"] - r["launch_ns"]
+                    phases[k, 2] = r["done_ns"] - r["arrival_ns"]
                 done["n"] += 1
                 done["matches"] += r["n_matches"]
                 done["bad"] += r["status"] != 0
-                phases.append((r["launch_ns"] - r["arrival_ns"], r["done_ns"] - r["launch_ns"],
-                               r["done_ns"] - r["arrival_ns"]))
-                if r["ticket"] in ticket_of:
-                    kept[ticket_of[r["ticket"]]] = r["keys"]
+                if r["keys"] is not None:
+                    got_keys[r["ticket"]] = r["keys"]
 
+    # no garbage collection pauses in the client while the stream runs (a pause delays
+    # submissions, which the latency, counted from the schedule, would show)
+    import gc
+    gc.collect()
+    gc.disable()
     th = threading.Thread(target=drain, daemon=True)
     th.start()
     t0 = time.monotonic_ns() + 20_000_000
@@ -306,8 +324,11 @@ def bench_serving(args):
                 busy += 1
             elif rc:
                 raise pfac.PfacError(rc, "pfac_server_submit")
-            elif i in verify_idx:
-                ticket_of[srv.last] = i
+            else:
+                if i in verify_idx:
+                    ticket_of[srv.last] = i
+                    verify_tickets.add(srv.last)
+                registered["max"] = srv.last
             i += 1
         if i < n_total:
             wait = (t0 + arr_ns[i] - time.monotonic_ns()) / 1e9
@@ -315,20 +336,23 @@ def bench_serving(args):
                 time.sleep(wait - 1e-4)
     th.join(timeout=120)
     stop.set()
+    gc.enable()
     st = srv.stats()
     srv.close()
     offered = 8.0 * sum(p[2] for p in ptrs) / (arr_ns[-1] / 1e9) / 1e9
     # every request has the same number of packets, so per-request percentiles are the
     # per-packet ones
-    ph = np.array(phases, dtype=np.float64).reshape(-1, 3) / 1e3
+    ph = phases[: min(done["n"], n_total)] / 1e3
     pct = (lambda col, q: round(float(np.percentile(ph[:, col], q)), 1) if len(ph) else None)
     mism = None
     if verify_idx:
         from oracle import native
         ac = native.AhoCorasick(w.patterns, w.alphabet)
-        mism = sum(not np.array_equal(kept.get(i, np.zeros(1, np.uint64) - 1),
+        kept = {i: got_keys.get(t) for t, i in ticket_of.items()}
+        missing = np.zeros(1, np.uint64) - np.uint64(1)
+        mism = sum(not np.array_equal(kept[i] if kept.get(i) is not None else missing,
                                       ac.scan_packets(w.requests[i].data, w.requests[i].offsets))
-                   for i in sorted(verify_idx))
+                   for i in sorted(kept))
     out = {
         "metric": METRIC, "value": round(st["bytes_per_s"] * 8 / 1e9, 3), "unit": "Gbit/s", "n_gpus": 1,
         "steps": n_total, "warmup": 64, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
@@ -336,7 +360,7 @@ def bench_serving(args):
         "data": "synthetic (seeded numpy generator; see DESIGN.md input recipe)",
         "config": {"workload": "serving_256", "description": WORKLOADS["serving_256"],
                    "requests": n_total, "patterns": len(w.patterns), "server": cfg,
-                   "plant_every": args.plant_every},
+                   "plant_every": args.plant_every, "slot_launch": "graph" if args.graph else "eager"},
         "serving": {"offered_gbit_s": round(offered, 3), "achieved_gbit_s": round(st["bytes_per_s"] * 8 / 1e9, 3),
                     "p50_us": round(st["p50_ns"] / 1e3, 1), "p99_us": round(st["p99_ns"] / 1e3, 1),
                     "max_us": round(st["max_ns"] / 1e3, 1), "requests_done": done["n"],
@@ -344,7 +368,7 @@ def bench_serving(args):
                     "mean_batch_kib": round(st["mean_batch_bytes"] / 1024, 1), "matches": done["matches"],
                     "queue_us": {"p50": pct(0, 50), "p99": pct(0, 99), "max": pct(0, 100)},
                     "service_us": {"p50": pct(1, 50), "p99": pct(1, 99), "max": pct(1, 100)},
-                    "verified_requests": len(verify_idx), "verify_mismatches": mism},
+                    "verified_requests": len(ticket_of), "verify_mismatches": mism},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -557,7 +581,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="serving: batch slots")
     ap.add_argument("--batch-mib", type=int, default=8, help="serving: MiB per batch")
     ap.add_argument("--plant-every", type=int, default=0, help="serving: planted variant")
-    ap.add_argument("--eager", action="store_true", help="serving: eager launch pairs instead of graph replays")
+    ap.add_argument("--graph", action="store_true",
+                    help="serving: slots replay captured graphs instead of enqueueing eager launch pairs")
     ap.add_argument("--verify", type=int, default=256,
                     help="serving: requests (evenly spread) whose keys are checked against the oracle")
     ap.add_argument("--sweep-mib", type=int, default=100, help="sweep: MiB per text")

@@ -348,10 +348,10 @@ PFAC_API void pfac_graph_destroy(pfac_graph *g);
 
 /* ------------------------------------------------------------------- serving loop
  * A server keeps the automaton resident on the current device and scans packet requests
- * as they arrive (continuous batching). Requests wait in a FIFO; a worker thread owns
- * `slots` batch slots, each with its own device buffers, stream and captured scan graph
- * (or, with PFAC_SERVER_EAGER, its own scan scratch sized for a full batch).
- * Whenever a slot is free, the worker packs every waiting request that fits
+ * as they arrive (continuous batching). Requests wait in a FIFO; the server owns `slots`
+ * batch slots, each with its own host thread, device buffers, stream and captured scan
+ * graph (or, with PFAC_SERVER_EAGER, its own scan scratch sized for a full batch).
+ * Whenever a slot is free, its thread packs every waiting request that fits
  * (max_batch_bytes / max_batch_packets) into one batch and launches it at once, so
  * requests that arrive while other batches run on the GPU are admitted as slots free up,
  * and the batches of different slots overlap on the device. Each packet is scanned as

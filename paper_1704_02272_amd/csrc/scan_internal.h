@@ -82,7 +82,10 @@ constexpr uint32_t kLdsF1 = kFilter2Words;                // word offset of the 
 constexpr uint32_t kAmask1 = (kFilterWordsMax - 1u) << 2; // byte-offset masks of the parts
 constexpr uint32_t kAmask2 = (kFilter2Words - 1u) << 2;
 constexpr uint32_t kGeneralWords = kFilter2Words + kFilterWordsMax;  // general filter words
-constexpr uint32_t kS3Words = 1u << 14;                   // sampled: 3-gram part (64 KiB)
+#ifndef PFAC_S3_LOG2
+#define PFAC_S3_LOG2 14
+#endif
+constexpr uint32_t kS3Words = 1u << PFAC_S3_LOG2;         // sampled: 3-gram part (64 KiB)
 constexpr uint32_t kS2Words = 1u << 11;                   // sampled: second-probe part (8 KiB)
 constexpr uint32_t kS1Words = 1u << 12;                   // sampled: first-probe part (16 KiB)
 constexpr uint32_t kLdsS2 = 0, kLdsS1 = kS2Words, kLdsS3 = kS2Words + kS1Words;

@@ -1,15 +1,17 @@
 // Serving loop: continuous batching of packet requests onto a resident automaton.
 //
-// Requests (a few packets each, copied at submit) wait in a FIFO. A worker thread owns
-// S slots; each slot holds the device memory for one batch (bytes, offsets, keys,
-// count, scratch), pinned staging, a stream and a captured scan graph that reads its
-// batch sizes from device memory. Whenever a slot is free and requests wait, the worker
-// packs as many waiting requests as fit into one batch and launches it at once, so
-// requests that arrive while other batches are on the GPU join the next free slot and
-// batches of different slots overlap on the device. The number of slots is what the
-// device-memory budget admits. A finished batch's keys are split back into requests
-// (keys are global byte offsets in the batch, so each request's keys form one run) and
-// reported with their arrival, launch and completion times.
+// Requests (a few packets each, copied at submit) wait in a FIFO. The server has S
+// slots, each with its own host thread; a slot holds the device memory for one batch
+// (bytes, offsets, keys, count, scratch), pinned staging, a stream and a captured scan
+// graph that reads its batch sizes from device memory (or scratch for eager launches).
+// Whenever a slot is free and requests wait, its thread packs as many waiting requests
+// as fit into one batch and launches it at once, so requests that arrive while other
+// batches are on the GPU join the next free slot and batches of different slots overlap
+// on the device; staging and finishing of different slots also overlap on the host. The
+// number of slots is what the device-memory budget admits. A finished batch's keys are
+// split back into requests (keys are global byte offsets in the batch, so each
+// request's keys form one run) and reported with their arrival, launch and completion
+// times.
 #include <string.h>
 
 #include <algorithm>
@@ -75,7 +77,7 @@ struct pfac_server {
     std::deque<Request *> pending;
     uint64_t pending_bytes = 0;
     std::deque<pfac_result> results;
-    std::thread worker;
+    std::vector<std::thread> workers;  // one per slot
     bool stop = false;
     int fatal = PFAC_OK;  // a device error stops the server; later calls report it
     std::atomic<uint64_t> next_ticket{1};
@@ -240,120 +242,90 @@ int finish_slot(pfac_server *sv, Slot &s, std::vector<pfac_result> &out) {
     return PFAC_OK;
 }
 
-void worker_main(pfac_server *sv) {
+// Results of a finished batch (or the failure of a batch) to the result queue and the
+// statistics. Caller holds mu.
+void publish(pfac_server *sv, Slot &s, int rc, std::vector<pfac_result> &fresh) {
+    if (rc && !sv->fatal) sv->fatal = rc;
+    for (size_t i = 0; i < s.reqs.size(); i++) {
+        Request *r = s.reqs[i];
+        if (rc) {
+            pfac_result e{};
+            e.ticket = r->ticket;
+            e.status = rc;
+            e.n_pkts = r->n_pkts;
+            e.n_bytes = r->bytes.size();
+            e.arrival_ns = r->arrival_ns;
+            e.launch_ns = s.launch_ns;
+            e.done_ns = now_ns();
+            sv->results.push_back(e);
+        }
+        delete r;
+    }
+    for (pfac_result &res : fresh) {
+        if (rc) {
+            free(res.keys);
+            continue;
+        }
+        sv->lat.push_back({res.done_ns > res.arrival_ns ? res.done_ns - res.arrival_ns : 0, res.n_pkts});
+        sv->st_requests++;
+        sv->st_packets += res.n_pkts;
+        sv->st_bytes += res.n_bytes;
+        sv->st_matches += res.n_matches;
+        if (!sv->st_first_arrival || res.arrival_ns < sv->st_first_arrival) sv->st_first_arrival = res.arrival_ns;
+        sv->st_last_done = std::max(sv->st_last_done, res.done_ns);
+        sv->results.push_back(res);
+    }
+    if (s.launch_ns) sv->st_busy_slot_ns += now_ns() - s.launch_ns;
+    s.reqs.clear();
+    if (sv->fatal) {
+        // fail whatever still waits
+        while (!sv->pending.empty()) {
+            Request *r = sv->pending.front();
+            sv->pending.pop_front();
+            pfac_result e{};
+            e.ticket = r->ticket;
+            e.status = sv->fatal;
+            e.n_pkts = r->n_pkts;
+            e.n_bytes = r->bytes.size();
+            e.arrival_ns = r->arrival_ns;
+            e.done_ns = now_ns();
+            sv->results.push_back(e);
+            delete r;
+        }
+        sv->pending_bytes = 0;
+        sv->cv_work.notify_all();
+    }
+    sv->cv_done.notify_all();
+}
+
+// One host thread per slot: whenever the slot is free and requests wait, it takes every
+// waiting request that fits one batch (continuous batching), stages and launches it,
+// waits for its completion event and publishes the results. Staging, launching and
+// finishing of different slots run in parallel, so no slot waits for another one's
+// host work.
+void slot_main(pfac_server *sv, size_t idx) {
     (void)hipSetDevice(sv->device);
+    Slot &s = sv->slots[idx];
     std::vector<pfac_result> fresh;
-    std::vector<Request *> finished;
     std::unique_lock<std::mutex> lk(sv->mu);
     for (;;) {
-        bool any_busy = false, progressed = false;
-        for (Slot &s : sv->slots) {
-            if (!s.busy) continue;
-            const hipError_t q = hipEventQuery(s.done);
-            if (q == hipErrorNotReady) {
-                any_busy = true;
-                continue;
-            }
-            s.busy = false;
-            progressed = true;
-            lk.unlock();
-            fresh.clear();
-            int rc = q == hipSuccess ? finish_slot(sv, s, fresh) : PFAC_EHIP;
-            lk.lock();
-            if (rc && !sv->fatal) sv->fatal = rc;
-            for (size_t i = 0; i < s.reqs.size(); i++) {
-                Request *r = s.reqs[i];
-                if (rc) {
-                    pfac_result e{};
-                    e.ticket = r->ticket;
-                    e.status = rc;
-                    e.n_pkts = r->n_pkts;
-                    e.n_bytes = r->bytes.size();
-                    e.arrival_ns = r->arrival_ns;
-                    e.launch_ns = s.launch_ns;
-                    e.done_ns = now_ns();
-                    sv->results.push_back(e);
-                }
-                delete r;
-            }
-            for (pfac_result &res : fresh) {
-                if (rc) {
-                    free(res.keys);
-                    continue;
-                }
-                sv->lat.push_back({res.done_ns > res.arrival_ns ? res.done_ns - res.arrival_ns : 0, res.n_pkts});
-                sv->st_requests++;
-                sv->st_packets += res.n_pkts;
-                sv->st_bytes += res.n_bytes;
-                sv->st_matches += res.n_matches;
-                if (!sv->st_first_arrival || res.arrival_ns < sv->st_first_arrival) sv->st_first_arrival = res.arrival_ns;
-                sv->st_last_done = std::max(sv->st_last_done, res.done_ns);
-                sv->results.push_back(res);
-            }
-            sv->st_busy_slot_ns += now_ns() - s.launch_ns;
-            s.reqs.clear();
-            sv->cv_done.notify_all();
+        sv->cv_work.wait(lk, [&] { return sv->stop || sv->fatal || !sv->pending.empty(); });
+        if (sv->fatal || sv->pending.empty()) {
+            if (sv->stop || sv->fatal) break;
+            continue;
         }
-        // continuous batching: every free slot takes what is waiting now
-        for (Slot &s : sv->slots) {
-            if (sv->pending.empty() || sv->fatal) break;
-            if (s.busy) continue;
-            take_requests(sv, s);
-            s.busy = true;
-            sv->st_batches++;
-            lk.unlock();
-            const int rc = launch_slot(sv, s);
-            lk.lock();
-            progressed = true;
-            if (rc) {
-                sv->fatal = rc;
-                // the requests packed into the failed launch are reported as failed
-                for (Request *r : s.reqs) {
-                    pfac_result e{};
-                    e.ticket = r->ticket;
-                    e.status = rc;
-                    e.n_pkts = r->n_pkts;
-                    e.n_bytes = r->bytes.size();
-                    e.arrival_ns = r->arrival_ns;
-                    e.done_ns = now_ns();
-                    sv->results.push_back(e);
-                    delete r;
-                }
-                s.reqs.clear();
-                s.busy = false;
-                sv->cv_done.notify_all();
-            } else {
-                any_busy = true;
-            }
-        }
-        if (sv->fatal) {
-            // fail whatever still waits
-            while (!sv->pending.empty()) {
-                Request *r = sv->pending.front();
-                sv->pending.pop_front();
-                pfac_result e{};
-                e.ticket = r->ticket;
-                e.status = sv->fatal;
-                e.n_pkts = r->n_pkts;
-                e.n_bytes = r->bytes.size();
-                e.arrival_ns = r->arrival_ns;
-                e.done_ns = now_ns();
-                sv->results.push_back(e);
-                delete r;
-            }
-            sv->pending_bytes = 0;
-            sv->cv_done.notify_all();
-        }
-        if (sv->stop && sv->pending.empty() && !any_busy) break;
-        if (progressed) continue;
-        if (any_busy) {
-            // batches in flight: poll their events again shortly
-            lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(5));
-            lk.lock();
-        } else {
-            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
-        }
+        take_requests(sv, s);
+        s.busy = true;
+        sv->st_batches++;
+        lk.unlock();
+        fresh.clear();
+        s.launch_ns = 0;
+        int rc = launch_slot(sv, s);
+        if (!rc && hipEventSynchronize(s.done) != hipSuccess) rc = PFAC_EHIP;
+        if (!rc) rc = finish_slot(sv, s, fresh);
+        lk.lock();
+        s.busy = false;
+        publish(sv, s, rc, fresh);
     }
 }
 
@@ -396,12 +368,19 @@ extern "C" int pfac_server_create(pfac_automaton *a, const pfac_server_config *c
         if (!rc) rc = alloc_slot(sv, s);
     if (!rc) {
         try {
-            sv->worker = std::thread(worker_main, sv);
+            for (size_t i = 0; i < sv->slots.size(); i++) sv->workers.emplace_back(slot_main, sv, i);
         } catch (...) {
             rc = PFAC_ENOMEM;
         }
     }
     if (rc) {
+        {
+            std::lock_guard<std::mutex> g(sv->mu);
+            sv->stop = true;
+        }
+        sv->cv_work.notify_all();
+        for (std::thread &t : sv->workers)
+            if (t.joinable()) t.join();
         for (Slot &s : sv->slots) free_slot(sv->a, s);
         delete sv;
         return rc;
@@ -530,7 +509,8 @@ extern "C" void pfac_server_destroy(pfac_server *sv) {
         sv->stop = true;
     }
     sv->cv_work.notify_all();
-    if (sv->worker.joinable()) sv->worker.join();
+    for (std::thread &t : sv->workers)
+        if (t.joinable()) t.join();
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(sv->device);

@@ -547,9 +547,10 @@ class Server:
         self.last = t.value
         return rc
 
-    def poll(self, timeout_us: int = 0, with_keys: bool = True) -> list:
+    def poll(self, timeout_us: int = 0, with_keys: bool = True, keys_for=None) -> list:
         """Finished requests: dicts with ticket, status, n_pkts, n_bytes, n_matches, keys
-        (uint64 numpy array), arrival_ns, launch_ns, done_ns."""
+        (uint64 numpy array), arrival_ns, launch_ns, done_ns. ``keys_for``: a predicate on
+        the ticket; keys are copied out only for the tickets it accepts (else None)."""
         n = C.c_uint32(0)
         _check(lib().pfac_server_poll(self.handle, self._buf, len(self._buf), C.byref(n), timeout_us),
                "pfac_server_poll")
@@ -557,7 +558,7 @@ class Server:
         for i in range(n.value):
             r = self._buf[i]
             keys = None
-            if with_keys:
+            if with_keys and (keys_for is None or keys_for(r.ticket)):
                 keys = (np.ctypeslib.as_array(r.keys, shape=(int(r.n_matches),)).copy()
                         if r.n_matches else np.zeros(0, dtype=np.uint64))
             out.append({"ticket": r.ticket, "status": r.status, "n_pkts": r.n_pkts, "n_bytes": r.n_bytes,
