@@ -574,6 +574,8 @@ def main():
     ap.add_argument("--algo", default="auto", choices=["auto", "plain", "tiled"])
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--streams", type=int, default=1, help="scan: streams the scans alternate over")
+    ap.add_argument("--no-pipelined", dest="pipelined", action="store_false",
+                    help="scan: skip the extra two-stream measurement")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="packets: skip the autotuner")
@@ -656,54 +658,58 @@ def main():
     # size the key buffer with one blocking scan
     first = pfac.pfac_scan(a, texts[0])
     count = int(first.numel())
-    # --streams S: scans go round-robin over S streams (each with its own key buffer and
-    # the library's scratch for that stream), so one scan's placement can run beside the
-    # next one's count kernel; every scan is still done inside the timed region
-    S = max(1, args.streams)
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
-    keys = [torch.empty(max(count, 1), dtype=torch.int64, device=dev) for _ in range(S)]
-    cnts = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(S)]
-    stream = streams[0]
-    cnt = cnts[0]
-
-    for i in range(max(args.warmup, S)):
-        pfac.pfac_scan_async(a, texts[i % len(texts)], keys[i % S], cnts[i % S], streams[i % S])
-    torch.cuda.synchronize()
-    # Two HIP events on the first scan stream bracket the K back-to-back scans (a timing
-    # event per scan would put its own barrier between the scans): device time per scan
-    # is their interval / K. With several streams the others wait for the first event and
-    # the first stream waits for all of them before the second.
-    # The C entry point is called with its arguments marshalled once, so the host keeps
-    # ahead of the device even on a loaded host.
     import ctypes
     scan_async = pfac.lib().pfac_scan_async
-    call_args = [(a.handle, ctypes.c_void_p(texts[i % len(texts)].data_ptr()), texts[i % len(texts)].numel(),
-                  ctypes.c_void_p(keys[i % S].data_ptr()), keys[i % S].numel(),
-                  ctypes.c_void_p(cnts[i % S].data_ptr()), ctypes.c_void_p(streams[i % S].cuda_stream))
-                 for i in range(len(texts) * S)]
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for st in streams[1:]:
-        st.wait_event(ev0)
-    bad = 0
-    for i in range(args.steps):
-        bad |= scan_async(*call_args[i % len(call_args)])
-    for st in streams[1:]:
-        e = torch.cuda.Event()
-        e.record(st)
-        stream.wait_event(e)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    if bad:
-        raise RuntimeError("pfac_scan_async failed in the timed loop (status bits %d)" % bad)
-    for c in cnts:
-        if int(c.item()) != count:
-            raise RuntimeError("match count changed between runs: %d vs %d" % (int(c.item()), count))
-    kern_ms_mean = ev0.elapsed_time(ev1) / args.steps
+
+    def timed_scans(S):
+        """K scans round-robin over S streams (each with its own key buffer and the
+        library's scratch for that stream; with S > 1 one scan's placement runs beside
+        the next one's count kernel, and every scan is still done inside the timed
+        region). Returns (wall seconds, event milliseconds) for the K scans.
+
+        Two HIP events on the first scan stream bracket the K back-to-back scans (a timing
+        event per scan would put its own barrier between the scans); the other streams wait
+        for the first event, and the first stream waits for all of them before the second.
+        The C entry point is called with its arguments marshalled once, so the host keeps
+        ahead of the device even on a loaded host."""
+        streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
+        keys = [torch.empty(max(count, 1), dtype=torch.int64, device=dev) for _ in range(S)]
+        cnts = [torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(S)]
+        stream = streams[0]
+        for i in range(max(args.warmup, S)):
+            pfac.pfac_scan_async(a, texts[i % len(texts)], keys[i % S], cnts[i % S], streams[i % S])
+        torch.cuda.synchronize()
+        call_args = [(a.handle, ctypes.c_void_p(texts[i % len(texts)].data_ptr()), texts[i % len(texts)].numel(),
+                      ctypes.c_void_p(keys[i % S].data_ptr()), keys[i % S].numel(),
+                      ctypes.c_void_p(cnts[i % S].data_ptr()), ctypes.c_void_p(streams[i % S].cuda_stream))
+                     for i in range(len(texts) * S)]
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for st in streams[1:]:
+            st.wait_event(ev0)
+        bad = 0
+        for i in range(args.steps):
+            bad |= scan_async(*call_args[i % len(call_args)])
+        for st in streams[1:]:
+            e = torch.cuda.Event()
+            e.record(st)
+            stream.wait_event(e)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if bad:
+            raise RuntimeError("pfac_scan_async failed in the timed loop (status bits %d)" % bad)
+        for c in cnts:
+            if int(c.item()) != count:
+                raise RuntimeError("match count changed between runs: %d vs %d" % (int(c.item()), count))
+        return wall, ev0.elapsed_time(ev1)
+
+    S = max(1, args.streams)
+    wall, ev_ms = timed_scans(S)
+    kern_ms_mean = ev_ms / args.steps
     ms_step = wall * 1e3 / args.steps
     gbit = 8.0 * n / (ms_step / 1e3) / 1e9
     avg_kern_s = kern_ms_mean / 1e3
@@ -734,8 +740,17 @@ def main():
                      "kernel_ms_mean": round(kern_ms_mean, 4),
                      "algorithmic_bytes_per_launch": int(alg_bytes)},
         "hbm_frac_of_peak": round(achieved / HBM_PEAK_GBS, 4),
+        "pipelined": None,
         "cpu_baseline": None,
     }
+    if S == 1 and args.pipelined:
+        # the same K scans alternating over two streams: the rate of a scanner that keeps
+        # two buffers in flight (one scan's placement beside the next one's count kernel)
+        w2, e2 = timed_scans(2)
+        out["pipelined"] = {"streams": 2, "value": round(8.0 * n / (w2 / args.steps) / 1e9, 2),
+                            "ms_per_step": round(w2 * 1e3 / args.steps, 4),
+                            "event_ms_per_scan": round(e2 / args.steps, 4),
+                            "hbm_frac": round(alg_bytes / (e2 / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)
