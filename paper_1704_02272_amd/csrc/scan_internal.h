@@ -48,7 +48,10 @@ constexpr uint32_t kRecMulti = 0x8000;  // record flag: several terminals (see S
 constexpr uint32_t kFastRecs = 8;    // a span with at most this many records is written by one lane
 constexpr uint32_t kDirectMaxSpans = 16384;  // placement without look-back up to this many spans
 constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement wave issues together
-constexpr uint32_t kPlaceThreads = 256;
+#ifndef PFAC_PLACE_THREADS
+#define PFAC_PLACE_THREADS 1024
+#endif
+constexpr uint32_t kPlaceThreads = PFAC_PLACE_THREADS;  // placement workgroup (its waves share a block's spans)
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
 constexpr uint32_t kStepLog2 = kLaneBytes == 16 ? 10 : 11;
 static_assert((1u << kStepLog2) == kStep, "step length is a power of two");

@@ -1136,6 +1136,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
     __shared__ uint64_t span_off[kBlockSpans];
     __shared__ uint32_t span_nh[kBlockSpans];
     __shared__ uint32_t span_cls[kBlockSpans];  // 0: no match, 1: one lane writes it, 2: a wave does
+    __shared__ uint32_t span_ovf[kBlockSpans];
     __shared__ uint32_t sh[4];
     __shared__ uint64_t pre[kPlaceWaves];
     if (sizes) {
@@ -1217,6 +1218,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             const uint64_t c = my_c;
             const uint32_t nh = my_nh, ovf = my_ovf;
             span_nh[lane] = nh;
+            span_ovf[lane] = ovf;
             span_cls[lane] = c == 0 ? 0u : (ovf == kNone && nh <= kFastRecs) ? 1u : 2u;
             const uint64_t inc = wave_incl_scan64(c);
             const uint64_t total = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(inc >> 32), 63) << 32) |
@@ -1308,7 +1310,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
             uint64_t run = span_off[i];
             const uint64_t a = (uint64_t)sp << span_log2;
             const uint64_t b = a + span_len < n ? a + span_len : n;
-            const uint32_t nh = so.nh[sp], ovf = so.ovf[sp];
+            const uint32_t nh = span_nh[i], ovf = span_ovf[i];
             // records kRecRounds x 64 at a time: every load of a round is issued before
             // any of its results is used, so a span with many records pays a few memory
             // latencies per 256 records rather than per 64
