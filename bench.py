@@ -573,6 +573,8 @@ def main():
     ap.add_argument("--workload", default="printable_256", choices=sorted(WORKLOADS))
     ap.add_argument("--algo", default="auto", choices=["auto", "plain", "tiled"])
     ap.add_argument("--copies", type=int, default=4)
+    ap.add_argument("--lane-bytes", type=int, default=0, choices=[0, 16, 32],
+                    help="scan: positions per thread and step (0: the library's default)")
     ap.add_argument("--streams", type=int, default=1, help="scan: streams the scans alternate over")
     ap.add_argument("--no-pipelined", dest="pipelined", action="store_false",
                     help="scan: skip the extra two-stream measurement")
@@ -629,8 +631,8 @@ def main():
     n = len(w.text)
     a = pfac.pfac_build(w.patterns, w.alphabet)
     info = pfac.pfac_table_info(a)
-    if args.algo != "auto":
-        pfac.pfac_set_tuning(a, algo=args.algo)
+    if args.algo != "auto" or args.lane_bytes:
+        pfac.pfac_set_tuning(a, algo=args.algo, lane_bytes=args.lane_bytes)
     if args.mode == "host":
         pinned = torch.empty(n, dtype=torch.uint8, pin_memory=True)
         pinned.numpy()[:] = w.text
@@ -733,7 +735,7 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "text_bytes": n, "patterns": len(w.patterns), "alphabet": w.alphabet,
                    "matches": count, "algo": algo, "text_copies_rotated": len(texts), "streams": S,
-                   "trie_nodes": info["n_nodes"]},
+                   "trie_nodes": info["n_nodes"], "lane_bytes": pfac.pfac_get_tuning(a)["lane_bytes"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,

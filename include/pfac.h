@@ -444,7 +444,8 @@ PFAC_API void pfac_server_destroy(pfac_server *s);
  *               as printed, kept as a baseline; single texts only), PFAC_ALGO_TILED
  *               (persistent count kernel with the LDS prefilter and root image, then the
  *               placement kernel).
- *   grid        workgroups of the count kernel (0 = as many as are resident at once).
+ *   grid        workgroups of the count kernel (0 = as many as are resident at once;
+ *               at most 2^24 - 1).
  *   span_log2   log2 of the bytes one wave scans as a unit (its chunk): 11..16; 0 = per
  *               scan, the longest span (4..64 KiB) that still gives every resident wave
  *               one. Smaller spans spread small texts over more waves; a span keeps up to
@@ -453,6 +454,10 @@ PFAC_API void pfac_server_destroy(pfac_server *s);
  *               or ..8 for alphabets <= 4); 0 = the builder's choice.
  *   filter_k    symbols per LDS prefilter key (root_depth..min(longest pattern, 4), or ..16
  *               for alphabets <= 4); 0 = the builder's choice for the root depth.
+ *   lane_bytes  positions per thread: the consecutive start positions (text bytes) each
+ *               lane of a wave takes per step, 16 (one 16-byte load) or 32 (two; 0 = 32).
+ *               The sampled prefilter form (bytes, no pattern shorter than 4) always takes
+ *               32, and pfac_get_tuning then reports 32. Results do not depend on it.
  * pfac_set_tuning with a new root_depth or filter_k rebuilds the LDS image and uploads it
  * to every device holding a copy; scans already queued and graphs already captured keep
  * the image and tuning they were launched or recorded with (old images are freed by
@@ -469,7 +474,8 @@ typedef struct {
     uint32_t span_log2;
     uint32_t root_depth;
     uint32_t filter_k;
-    uint32_t reserved[3];
+    uint32_t lane_bytes;
+    uint32_t reserved[2];
 } pfac_tuning;
 
 PFAC_API int pfac_set_tuning(pfac_automaton *a, const pfac_tuning *t);
@@ -478,9 +484,9 @@ PFAC_API int pfac_get_tuning(const pfac_automaton *a, pfac_tuning *t);
 /* pfac_tune -- measure the tiled scan on a sample workload already in device memory (a
  * text when d_offsets is NULL, else a packet batch as in pfac_scan_batch) and keep the
  * fastest tuning: coordinate descent over span_log2, then root_depth, then filter_k, then
- * grid, each point timed with HIP events over `reps` scans (0 = 5) after one warm-up, on
- * `stream`. Every point must reproduce the match count of the first scan, else
- * PFAC_EINTERNAL. The tuner allocates its own key buffer (freed on return) and may grow
+ * lane_bytes, then grid, each point timed with HIP events over `reps` scans (0 = 5) after
+ * one warm-up, on `stream`. Every point must reproduce the match count and an
+ * order-sensitive digest of the keys of the first scan, else PFAC_EINTERNAL. The tuner allocates its own key buffer (freed on return) and may grow
  * the stream's scratch. On success the automaton keeps the best point, *out receives it
  * (as pfac_get_tuning) and *out_ms (if not NULL) its mean milliseconds per scan; on error
  * the previous tuning is restored. No other host thread may scan with this automaton

@@ -28,7 +28,7 @@ extern "C" const char *pfac_strerror(int status) {
     }
 }
 
-extern "C" int pfac_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+extern "C" int pfac_version(void) { return 1 * 10000 + 1 * 100 + 0; }
 
 extern "C" int pfac_build(const uint8_t *const *pats, const uint64_t *lens, uint32_t n_pats,
                           uint32_t alphabet, pfac_automaton **out) {

@@ -160,6 +160,7 @@ struct pfac_automaton {
     uint32_t layout = 0, nw = 0;  // nw: 64-bit bitmap words per node (WIDE)
     uint32_t algo = 0, grid = 0;  // tuning: kernel choice, persistent grid (0 = auto)
     uint32_t span_log2 = 0;       // tuning: log2 of the count kernel's span length (0 = by text size)
+    uint32_t lane_bytes = 32;     // tuning: positions per thread and wave step (16 or 32)
     uint32_t req_depth = 0, req_k = 0;  // tuning: requested root depth / filter key (0 = builder's)
     // The patterns as given (CSR), kept to rebuild the LDS image when tuning asks.
     std::vector<uint8_t> pat_bytes;

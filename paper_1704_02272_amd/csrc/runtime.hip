@@ -30,6 +30,25 @@ namespace {
 
 __global__ void set_u64_kernel(uint64_t *dst, uint64_t v) { *dst = v; }
 
+// Order-sensitive digest of the first min(*count, cap) keys: the wrapping sum over i of
+// SplitMix64's output mix applied to key_i ^ (i * golden ratio). The autotuner compares it
+// with the first scan's, so a candidate tuning must reproduce the keys, not only their
+// count. *out must be zero before the launch.
+__global__ void keys_digest_kernel(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ count, uint64_t cap,
+                                   unsigned long long *out) {
+    uint64_t n = *count;
+    if (n > cap) n = cap;
+    uint64_t acc = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t z = keys[i] ^ (i * 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        acc += z ^ (z >> 31);
+    }
+    for (int o = 32; o; o >>= 1) acc += __shfl_xor((unsigned long long)acc, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, (unsigned long long)acc);
+}
+
 int check_device(int device) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return PFAC_ENODEVICE;
@@ -359,7 +378,7 @@ static int scan_enqueue(pfac_automaton *a, const uint8_t *d_text, uint64_t n, co
     const uint64_t ns = (n + (1ull << span_log2) - 1) >> span_log2;
     const uint32_t grid = a->grid ? (uint32_t)std::min<uint64_t>(a->grid, (ns + kWaves - 1) / kWaves) : 0u;
     if (launch_tiled(c->view, d_text, n, d_offsets, n_pkts, d_keys, cap, cnt, w->so, w->ts, nullptr, grid,
-                     span_log2, s))
+                     span_log2, a->lane_bytes, s))
         return PFAC_EHIP;
     w->launches++;
     return PFAC_OK;
@@ -449,7 +468,8 @@ extern "C" int pfac_scan_noalloc(pfac_automaton *a, const uint8_t *d_text, uint6
     // every span's count, record count and overflow are written by the count kernel
     // before the placement reads them, and placement of this many spans uses no
     // look-back state: nothing in the array needs clearing between calls
-    if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, d_count, so, ts, nullptr, grid, span_log2, s))
+    if (launch_tiled(c->view, d_text, n, nullptr, 0, d_keys, cap, d_count, so, ts, nullptr, grid, span_log2,
+                     a->lane_bytes, s))
         return PFAC_EHIP;
     return PFAC_OK;
 }
@@ -501,10 +521,11 @@ extern "C" int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, cons
     if (!g) return PFAC_ENOMEM;
     g->a = a;
     DevTable view{};
-    uint32_t span_log2 = kSpanLog2, grid = 0;
+    uint32_t span_log2 = kSpanLog2, grid = 0, lane_bytes = 32;
     {
         std::lock_guard<std::mutex> lk(a->mu);
         grid = a->grid;
+        lane_bytes = a->lane_bytes;
         DeviceCopy *c = nullptr;
         int rc = get_copy(a, &c);
         if (rc) {
@@ -521,7 +542,7 @@ extern "C" int pfac_graph_create(pfac_automaton *a, const uint8_t *d_bytes, cons
     if (!rc && hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = PFAC_EHIP;
     if (!rc) {
         const int lr = launch_tiled(view, d_bytes, max_bytes, d_offsets, d_offsets ? max_pkts : 0, d_keys, cap,
-                                    d_count, g->ws.so, g->ws.ts, d_sizes, grid, span_log2, s);
+                                    d_count, g->ws.so, g->ws.ts, d_sizes, grid, span_log2, lane_bytes, s);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(s, &graph);
         g->graph = graph;
@@ -591,6 +612,8 @@ static int set_tuning_locked(pfac_automaton *a, const pfac_tuning *t) {
     if (t->algo == PFAC_ALGO_PLAIN && a->merge_levels) return PFAC_EINVAL;  // the baseline walks the plain trie
     const uint32_t span = t->span_log2;  // 0: chosen per scan from the text size
     if (span && (span < kMinSpanLog2 || span > kMaxSpanLog2)) return PFAC_EINVAL;
+    if (t->lane_bytes != 0 && t->lane_bytes != 16 && t->lane_bytes != 32) return PFAC_EINVAL;
+    if (t->grid > 0xffffffu) return PFAC_EINVAL;
     if (t->root_depth != a->req_depth || t->filter_k != a->req_k) {
         int rc = rebuild_lds_image(a, t->root_depth, t->filter_k);
         if (rc) {
@@ -606,6 +629,7 @@ static int set_tuning_locked(pfac_automaton *a, const pfac_tuning *t) {
     a->algo = t->algo;
     a->grid = t->grid;
     a->span_log2 = span;
+    a->lane_bytes = t->lane_bytes == 16 ? 16u : 32u;
     return PFAC_OK;
 }
 
@@ -623,6 +647,8 @@ extern "C" int pfac_get_tuning(const pfac_automaton *a, pfac_tuning *t) {
     t->span_log2 = a->span_log2;
     t->root_depth = a->shape.root_depth;
     t->filter_k = a->shape.filter_k ? a->shape.filter_k : a->shape.root_depth;
+    // the sampled prefilter form takes 32 bytes a lane whatever was asked for
+    t->lane_bytes = a->shape.sampled ? 32u : a->lane_bytes;
     return PFAC_OK;
 }
 
@@ -637,8 +663,9 @@ struct TuneRun {
     uint32_t n_pkts;
     uint32_t reps;
     hipStream_t s;
-    uint64_t *d_keys = nullptr, cap = 0, *d_count = nullptr;
-    uint64_t want = ~0ull;  // the match count every candidate must reproduce
+    uint64_t *d_keys = nullptr, cap = 0, *d_count = nullptr, *d_digest = nullptr;
+    uint64_t want = ~0ull;         // the match count every candidate must reproduce
+    uint64_t want_digest = 0;      // and the digest of its keys
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 
@@ -648,8 +675,18 @@ int tune_enqueue(TuneRun &r) {
     return scan_enqueue(r.a, r.d_bytes, r.n, nullptr, 0, r.d_keys, r.cap, r.d_count, r.s, nullptr);
 }
 
+// Digest of the keys of the last scan enqueued (see keys_digest_kernel), on the host.
+int tune_digest(TuneRun &r, uint64_t *out) {
+    if (launch_set_u64(r.d_digest, 0, r.s)) return PFAC_EHIP;
+    keys_digest_kernel<<<64, 256, 0, r.s>>>(r.d_keys, r.d_count, r.cap, (unsigned long long *)r.d_digest);
+    if (hipGetLastError() != hipSuccess) return PFAC_EHIP;
+    if (hipMemcpyAsync(out, r.d_digest, 8, hipMemcpyDeviceToHost, r.s) != hipSuccess) return PFAC_EHIP;
+    return hipStreamSynchronize(r.s) == hipSuccess ? PFAC_OK : PFAC_EHIP;
+}
+
 // Mean milliseconds per scan under the automaton's current tuning (one warm-up scan, then
-// `reps` timed). Checks that the count is the one every other candidate produced.
+// `reps` timed). Checks that the count and the keys' digest are the ones every other
+// candidate produced.
 int tune_measure(TuneRun &r, float *ms) {
     int rc = tune_enqueue(r);
     if (rc) return rc;
@@ -663,6 +700,9 @@ int tune_measure(TuneRun &r, float *ms) {
     if (hipMemcpy(&cnt, r.d_count, 8, hipMemcpyDeviceToHost) != hipSuccess) return PFAC_EHIP;
     if (cnt == kCountTimeout) return PFAC_ETIMEOUT;
     if (cnt != r.want) return PFAC_EINTERNAL;
+    uint64_t dg = 0;
+    if ((rc = tune_digest(r, &dg))) return rc;
+    if (dg != r.want_digest) return PFAC_EINTERNAL;
     *ms = t / (float)r.reps;
     return PFAC_OK;
 }
@@ -696,6 +736,10 @@ extern "C" int pfac_tune(pfac_automaton *a, const uint8_t *d_bytes, uint64_t n_b
     // the match count under the current tuning sizes the key buffer and is the answer
     // every candidate has to reproduce
     if (hipMalloc(&r.d_count, 8) != hipSuccess) return PFAC_ENOMEM;
+    if (hipMalloc(&r.d_digest, 8) != hipSuccess) {
+        hipFree(r.d_count);
+        return PFAC_ENOMEM;
+    }
     if (hipEventCreate(&r.e0) != hipSuccess || hipEventCreate(&r.e1) != hipSuccess) rc = PFAC_EHIP;
     if (!rc) rc = tune_enqueue(r);
     if (!rc && hipMemcpyAsync(&r.want, r.d_count, 8, hipMemcpyDeviceToHost, r.s) != hipSuccess) rc = PFAC_EHIP;
@@ -705,13 +749,17 @@ extern "C" int pfac_tune(pfac_automaton *a, const uint8_t *d_bytes, uint64_t n_b
         r.cap = r.want;
         if (r.cap && hipMalloc(&r.d_keys, r.cap * 8) != hipSuccess) rc = PFAC_ENOMEM;
     }
+    // the keys under the starting tuning, whose digest every candidate must reproduce
+    if (!rc) rc = tune_enqueue(r);
+    if (!rc) rc = tune_digest(r, &r.want_digest);
     pfac_tuning best = start;
     best.algo = PFAC_ALGO_TILED;
     best.root_depth = a->req_depth;
     best.filter_k = a->req_k;
     float best_ms = 0.f;
     if (!rc) rc = tune_try(r, best, &best_ms);
-    // coordinate descent: span length, then root depth, then filter key, then grid
+    // coordinate descent: span length, then root depth, then filter key, then positions
+    // per thread, then grid
     const bool pack2 = a->alphabet <= 4;
     const uint32_t dmax = std::min(a->min_len, pack2 ? 8u : 2u);
     const uint32_t kmax = std::min(a->max_len, pack2 ? 16u : 4u);
@@ -750,6 +798,11 @@ extern "C" int pfac_tune(pfac_automaton *a, const uint8_t *d_bytes, uint64_t n_b
         }
     }
     {
+        pfac_tuning c = best;
+        c.lane_bytes = best.lane_bytes == 16 ? 32u : 16u;
+        consider(c);
+    }
+    {
         int dev = 0, cus = 256;
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -769,6 +822,7 @@ extern "C" int pfac_tune(pfac_automaton *a, const uint8_t *d_bytes, uint64_t n_b
     if (r.e1) hipEventDestroy(r.e1);
     hipFree(r.d_keys);
     hipFree(r.d_count);
+    hipFree(r.d_digest);
     if (!rc) {
         (void)pfac_get_tuning(a, out);
         if (out_ms) *out_ms = best_ms;

@@ -31,17 +31,23 @@ namespace pfac {
 
 constexpr uint32_t kThreads = PFAC_SCAN_THREADS;  // workgroup: waves sharing one LDS image
 constexpr uint32_t kWaves = kThreads / 64;
-#ifndef PFAC_LANE_BYTES
-#define PFAC_LANE_BYTES 32
-#endif
-constexpr uint32_t kLaneBytes = PFAC_LANE_BYTES;  // bytes (starts) a lane takes per step: 16 or 32
-static_assert(kLaneBytes == 16 || kLaneBytes == 32, "a lane's starts fit one 32-bit mask");
-constexpr uint32_t kStep = 64 * kLaneBytes;  // bytes a wave streams per step
 constexpr uint32_t kSpanLog2 = 14;   // default bytes per work unit (a wave's span): 16 KiB
-constexpr uint32_t kMinSpanLog2 = kLaneBytes == 16 ? 10 : 11;  // a span holds at least one wave step
+constexpr uint32_t kMinSpanLog2 = 11; // a span holds at least one wave step
 constexpr uint32_t kMaxSpanLog2 = 16; // span-local starts are 16-bit
-constexpr uint32_t kPrefetch = PFAC_PREFETCH;  // text loads in flight per lane, in wave steps (>= 2)
+constexpr uint32_t kPrefetch = PFAC_PREFETCH;  // wave steps of 2 KiB whose loads are in flight (>= 2)
 static_assert(PFAC_PREFETCH >= 2, "the next step's first word comes from the prefetch");
+
+// Positions per thread: the bytes (starts) a lane takes per wave step, 32 (two 16-byte
+// loads; the default) or 16 (one load). A tuning choice for every prefilter form but the
+// sampled one, whose candidate checks read a lane's 32 bytes. The bytes a wave keeps in
+// flight are the same either way (kPrefetch x 2 KiB).
+constexpr uint32_t kLaneBytes = 32;
+template <uint32_t LB>
+struct Lanes {
+    static_assert(LB == 16 || LB == 32, "a lane's starts fit one 32-bit mask");
+    static constexpr uint32_t step = 64 * LB;                    // bytes a wave streams per step
+    static constexpr uint32_t prefetch = kPrefetch * (32 / LB);  // steps whose loads are in flight
+};
 constexpr uint32_t kHCapMinLog2 = 8; // match records kept per span: span / 64, at least 256
 constexpr uint32_t kBlockSpans = 64; // spans per placement block (one per lane of a wave)
 constexpr uint32_t kRecMulti = 0x8000;  // record flag: several terminals (see SpanOut)
@@ -53,8 +59,6 @@ constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement
 #endif
 constexpr uint32_t kPlaceThreads = PFAC_PLACE_THREADS;  // placement workgroup (its waves share a block's spans)
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
-constexpr uint32_t kStepLog2 = kLaneBytes == 16 ? 10 : 11;
-static_assert((1u << kStepLog2) == kStep, "step length is a power of two");
 
 // LDS of the scan kernel (32-bit words), one of two layouts per kernel instance (a
 // probe's masked hash plus its part's compile-time offset is its byte address; every
@@ -219,14 +223,15 @@ constexpr uint64_t kCountOverflow = ~0ull - 1;
 // bounded by the n / n_packets given here (graph replays). grid: workgroups of the
 // count kernel (0 = as many as are resident at once). span_log2: log2 of the span length,
 // kMinSpanLog2..kMaxSpanLog2 (else -1, nothing launched); the scratch in `so` must hold
-// ceil(n / 2^span_log2) spans.
+// ceil(n / 2^span_log2) spans. lane_bytes: positions per thread and step, 16 or 32 (any
+// other value: 32; the sampled form always takes 32).
 int launch_tiled(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                  uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-                 const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s);
+                 const uint64_t *sizes, uint32_t grid, uint32_t span_log2, uint32_t lane_bytes, hipStream_t s);
 // The same for a compressed table (t.merged; launch_tiled dispatches to it).
 int launch_tiled_merged(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets,
                         uint32_t n_packets, uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so,
                         const TileState &ts, const uint64_t *sizes, uint32_t grid, uint32_t span_log2,
-                        hipStream_t s);
+                        uint32_t lane_bytes, hipStream_t s);
 
 }  // namespace pfac

@@ -718,8 +718,9 @@ struct SpanState {
     uint64_t top;     // starts at or past top are not counted here
 };
 
-template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED>
+template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED, uint32_t LB>
 struct Scanner {
+    static constexpr uint32_t kLB = LB, kSt = Lanes<LB>::step, kPf = Lanes<LB>::prefetch;
     const DevTable &t;
     static constexpr bool kSampled = FM == FM_K4 && !PACK2;
     static constexpr int kForm = FormOf<PACK2, FM>::value;
@@ -734,10 +735,10 @@ struct Scanner {
     bool aligned;
     uint32_t *stg;  // sampled form: this wave's step staging words (kStageWords)
 
-    // A lane's bytes of one step: kLaneBytes (16 or 32) consecutive text bytes, with the
+    // A lane's bytes of one step: kLB (16 or 32) consecutive text bytes, with the
     // two-bit codes of each 16 when symbols are two-bit codes.
     struct Chunk {
-        uint4 v[kLaneBytes / 16];
+        uint4 v[kLB / 16];
     };
 
     __device__ __forceinline__ uint64_t end_of(uint64_t s) const {
@@ -887,7 +888,7 @@ struct Scanner {
     // any further ones (rare). Starts whose 4-gram passes join the survivor queue.
     __device__ __forceinline__ void sample_step(SpanState &S, uint64_t step, const Chunk &cur, uint32_t nd,
                                                 uint32_t m, uint32_t sl0) {
-        static_assert(kLaneBytes == 32, "the sampled check reads a lane's 32 bytes");
+        static_assert(kLB == 32, "the sampled check reads a lane's 32 bytes");
         if (!__ballot(m != 0)) return;
         // the lane's 36 bytes to its staging words (read back only by this lane; the
         // wave's LDS operations complete in order, so no barrier is needed either way)
@@ -915,9 +916,9 @@ struct Scanner {
         }
         // the span's last step: keep starts below top
         // span-local and 32-bit (scalar); top can lie before the span start
-        if ((uint32_t)(step - S.a) + kStep > (S.top > S.a ? (uint32_t)(S.top - S.a) : 0u)) {
+        if ((uint32_t)(step - S.a) + kSt > (S.top > S.a ? (uint32_t)(S.top - S.a) : 0u)) {
             const uint64_t s0 = S.a + sl0;
-            if (s0 + kLaneBytes > S.top) sm &= s0 >= S.top ? 0u : (uint32_t)((1ull << (uint32_t)(S.top - s0)) - 1ull);
+            if (s0 + kLB > S.top) sm &= s0 >= S.top ? 0u : (uint32_t)((1ull << (uint32_t)(S.top - s0)) - 1ull);
         }
         take(S, sm, sl0);
     }
@@ -936,38 +937,38 @@ struct Scanner {
     __device__ __forceinline__ Chunk chunk_buffer(__amdgpu_buffer_rsrc_t rs, uint32_t loff, uint32_t soff) const {
         Chunk c;
 #pragma unroll
-        for (uint32_t h = 0; h < kLaneBytes / 16; h++) c.v[h] = stream16(rs, loff + 16 * h, soff);
+        for (uint32_t h = 0; h < kLB / 16; h++) c.v[h] = stream16(rs, loff + 16 * h, soff);
         return c;
     }
     __device__ __forceinline__ Chunk chunk_guarded(uint64_t p, uint64_t ld) const {
         Chunk c;
 #pragma unroll
-        for (uint32_t h = 0; h < kLaneBytes / 16; h++) c.v[h] = load16(text, p + 16 * h, ld, aligned);
+        for (uint32_t h = 0; h < kLB / 16; h++) c.v[h] = load16(text, p + 16 * h, ld, aligned);
         return c;
     }
 
-    // Survivor mask of this lane's kLaneBytes starts at `step` (bit j = start
-    // step + kLaneBytes * lane + j), cut to [S.a, top). next_d0 / next_c: first word / first
+    // Survivor mask of this lane's kLB starts at `step` (bit j = start
+    // step + kLB * lane + j), cut to [S.a, top). next_d0 / next_c: first word / first
     // two-bit codes of the bytes after this lane's.
     __device__ __forceinline__ uint32_t mask_step(const SpanState &S, uint64_t step, uint64_t top, const Chunk &cur,
                                                   uint32_t next_d0, uint32_t next_c, uint32_t *sl0_out) const {
         const uint32_t lane = lane_id();
         uint32_t m = 0;
 #pragma unroll
-        for (uint32_t h = 0; h < kLaneBytes / 16; h++) {
-            const bool lasth = h + 1 == kLaneBytes / 16;
+        for (uint32_t h = 0; h < kLB / 16; h++) {
+            const bool lasth = h + 1 == kLB / 16;
             const uint32_t nd = lasth ? next_d0 : cur.v[h + 1].x;
             const uint32_t c0 = PACK2 ? pack2x16(cur.v[h]) : 0u;
             const uint32_t c1 = PACK2 ? (lasth ? next_c : pack2x16(cur.v[h + 1])) : 0u;
             m |= prefilter16<PACK2, FM>(t, W.img, cur.v[h], nd, c0, c1) << (16 * h);
         }
-        const uint32_t sl0 = (uint32_t)(step - S.a) + kLaneBytes * lane;  // span-local start of bit 0
+        const uint32_t sl0 = (uint32_t)(step - S.a) + kLB * lane;  // span-local start of bit 0
         // last step: keep starts below top (a candidate j while j-1 is below it)
         const uint64_t cut = FM == FM_K4 && !PACK2 ? top + 1 : top;
         // span-local and 32-bit (scalar); cut can lie before the span start
-        if ((uint32_t)(step - S.a) + kStep > (cut > S.a ? (uint32_t)(cut - S.a) : 0u)) {
+        if ((uint32_t)(step - S.a) + kSt > (cut > S.a ? (uint32_t)(cut - S.a) : 0u)) {
             const uint64_t s0 = S.a + sl0;
-            if (s0 + kLaneBytes > cut) m &= s0 >= cut ? 0u : (uint32_t)((1ull << (uint32_t)(cut - s0)) - 1ull);
+            if (s0 + kLB > cut) m &= s0 >= cut ? 0u : (uint32_t)((1ull << (uint32_t)(cut - s0)) - 1ull);
         }
         *sl0_out = sl0;
         return m;
@@ -994,44 +995,44 @@ struct Scanner {
     __device__ __forceinline__ void stream(SpanState &S, uint64_t hi) {
         const uint32_t lane = lane_id();
         uint64_t step = S.a;
-        const uint64_t hiR = (hi + kStep - 1) & ~(uint64_t)(kStep - 1);  // end of the last step
+        const uint64_t hiR = (hi + kSt - 1) & ~(uint64_t)(kSt - 1);  // end of the last step
         const uint64_t top = hi < lim ? hi : lim;
         S.top = top;
         if (aligned && hiR + 16 <= n) {
             // Steady state: every load is an unconditional 16-byte load with no per-lane
-            // test, kPrefetch steps ahead; addresses past the span are clamped to its last
+            // test, kPf steps ahead; addresses past the span are clamped to its last
             // step (a repeated load, no bytes past the span). Only the 16 bytes right
             // after the span are read for the last starts' windows.
-            const uint64_t lastst = hiR - kStep;
+            const uint64_t lastst = hiR - kSt;
             const uint4 after = *reinterpret_cast<const uint4 *>(text + hiR);  // uniform address
             const __amdgpu_buffer_rsrc_t rs = text_rsrc(text, n);
-            const uint32_t loff = kLaneBytes * lane;
-            Chunk buf[kPrefetch];  // buf[0]: this step; buf[i]: i steps ahead
+            const uint32_t loff = kLB * lane;
+            Chunk buf[kPf];  // buf[0]: this step; buf[i]: i steps ahead
 #pragma unroll
-            for (uint32_t i = 0; i < kPrefetch; i++)
-                buf[i] = chunk_buffer(rs, loff, (uint32_t)(step + i * kStep < lastst ? step + i * kStep : lastst));
+            for (uint32_t i = 0; i < kPf; i++)
+                buf[i] = chunk_buffer(rs, loff, (uint32_t)(step + i * kSt < lastst ? step + i * kSt : lastst));
             const uint32_t last32 = (uint32_t)lastst;  // the text is below 4 GiB
-            for (; step < hiR; step += kStep) {
-                // kPrefetch steps ahead, clamped to the last step (32-bit scalar arithmetic;
+            for (; step < hiR; step += kSt) {
+                // kPf steps ahead, clamped to the last step (32-bit scalar arithmetic;
                 // step <= lastst here, so the difference does not wrap)
                 const uint32_t st32 = (uint32_t)step;
-                const uint32_t ak = last32 - st32 > kPrefetch * kStep ? st32 + kPrefetch * kStep : last32;
+                const uint32_t ak = last32 - st32 > kPf * kSt ? st32 + kPf * kSt : last32;
                 const Chunk nxk = chunk_buffer(rs, loff, ak);
                 uint32_t nd, nc;
-                next_lane_head(buf[0], buf[1 % kPrefetch], step == lastst, after, &nd, &nc);
+                next_lane_head(buf[0], buf[1 % kPf], step == lastst, after, &nd, &nc);
                 step_body(S, step, top, buf[0], nd, nc);
 #pragma unroll
-                for (uint32_t i = 0; i + 1 < kPrefetch; i++) buf[i] = buf[i + 1];
-                buf[kPrefetch - 1] = nxk;
+                for (uint32_t i = 0; i + 1 < kPf; i++) buf[i] = buf[i + 1];
+                buf[kPf - 1] = nxk;
             }
         } else {
             // End of the text, or an unaligned text: guarded loads, zero past the end.
             const uint64_t need = hi + (PACK2 ? 16 : 4);
             const uint64_t ld = need < n ? need : n;
-            Chunk cur = chunk_guarded(step + kLaneBytes * lane, ld);
-            Chunk nx1 = chunk_guarded(step + kStep + kLaneBytes * lane, ld);
-            for (; step < hi; step += kStep) {
-                const Chunk nx2 = chunk_guarded(step + 2 * kStep + kLaneBytes * lane, ld);
+            Chunk cur = chunk_guarded(step + kLB * lane, ld);
+            Chunk nx1 = chunk_guarded(step + kSt + kLB * lane, ld);
+            for (; step < hi; step += kSt) {
+                const Chunk nx2 = chunk_guarded(step + 2 * kSt + kLB * lane, ld);
                 uint32_t nd, nc;
                 next_lane_head(cur, nx1, false, make_uint4(0u, 0u, 0u, 0u), &nd, &nc);
                 step_body(S, step, top, cur, nd, nc);
@@ -1048,7 +1049,7 @@ struct Scanner {
 };
 
 // ------------------------------------------------------------------ count kernel
-template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED>
+template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED, uint32_t LB>
 __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTable t, const uint8_t *__restrict__ text, uint64_t n,
                                                       const uint64_t *__restrict__ offsets, uint32_t n_packets,
                                                       SpanOut so, const uint64_t *__restrict__ sizes,
@@ -1107,7 +1108,7 @@ __global__ __launch_bounds__(kThreads, PFAC_SCAN_MIN_WG) void scan_count(DevTabl
     uint16_t *wq = reinterpret_cast<uint16_t *>(img + L::queues) + wave * L::qcap;
     uint32_t *stg = nullptr;
     if constexpr (FormOf<PACK2, FM>::value == kFormSampled) stg = img + L::stage + wave * kStageWords;
-    Scanner<LAYOUT, PACK2, SEG, FM, MERGED> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
+    Scanner<LAYOUT, PACK2, SEG, FM, MERGED, LB> sc{t, {t, text, img}, text, n, n >= t.min_len ? n - t.min_len + 1 : 0,
                                    offsets, n_packets, so, wq, (((uintptr_t)text) & 15) == 0, stg};
     const uint32_t waves = gridDim.x * kWaves;
     for (uint32_t span = blockIdx.x * kWaves + wave; span < n_spans; span += waves) {
@@ -1410,13 +1411,13 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
     }
 }
 
-template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED>
+template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED, uint32_t LB>
 int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
                const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s) {
     const uint64_t n_spans = (n + (1ull << span_log2) - 1) >> span_log2;
     const uint64_t n_blocks = (n_spans + kBlockSpans - 1) / kBlockSpans;
-    auto kc = scan_count<LAYOUT, PACK2, SEG, FM, MERGED>;
+    auto kc = scan_count<LAYOUT, PACK2, SEG, FM, MERGED, LB>;
     auto kp = place_emit<LAYOUT, SEG, MERGED>;
     static std::once_flag once;
     static int cus = 0, per_cu = 1, per_cu_p = 1;
@@ -1447,19 +1448,34 @@ int launch_one(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Positions per thread: 16 bytes a lane and step when asked for and the form allows it
+// (the sampled form reads a lane's 32 bytes), else 32.
+template <int LAYOUT, bool PACK2, bool SEG, int FM, bool MERGED>
+int launch_lanes(uint32_t lane_bytes, const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets,
+                 uint32_t n_packets, uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so,
+                 const TileState &ts, const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s) {
+    if constexpr (!(FM == FM_K4 && !PACK2)) {
+        if (lane_bytes == 16)
+            return launch_one<LAYOUT, PACK2, SEG, FM, MERGED, 16>(t, text, n, offsets, n_packets, keys, cap, d_count,
+                                                                  so, ts, sizes, grid, span_log2, s);
+    }
+    return launch_one<LAYOUT, PACK2, SEG, FM, MERGED, 32>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts,
+                                                          sizes, grid, span_log2, s);
+}
+
 // Every kernel instance for one kind of table (plain or compressed).
 template <bool MERGED>
 int launch_tiled_t(const DevTable &t, const uint8_t *text, uint64_t n, const uint64_t *offsets, uint32_t n_packets,
                    uint64_t *keys, uint64_t cap, uint64_t *d_count, const SpanOut &so, const TileState &ts,
-                   const uint64_t *sizes, uint32_t grid, uint32_t span_log2, hipStream_t s) {
+                   const uint64_t *sizes, uint32_t grid, uint32_t span_log2, uint32_t lane_bytes, hipStream_t s) {
     if (span_log2 < kMinSpanLog2 || span_log2 > kMaxSpanLog2) return -1;
     const bool seg = offsets != nullptr;
     const bool narrow = t.layout == LAYOUT_NARROW;
     const bool pack2 = t.pack2 != 0;
     const int fm = t.filter_k == 0 ? FM_ROOT : t.sampled ? FM_K4 : t.exact ? FM_EXACT : FM_GEN;
 #define PFAC_L(LA, P2, SG, F) \
-    return launch_one<LA, P2, SG, F, MERGED>(t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, sizes, grid, \
-                                             span_log2, s)
+    return launch_lanes<LA, P2, SG, F, MERGED>(lane_bytes, t, text, n, offsets, n_packets, keys, cap, d_count, so, ts, \
+                                               sizes, grid, span_log2, s)
     // two-bit symbols: the exact, hashed and root-only forms; bytes: sampled, hashed, root-only
 #define PFAC_FM2(LA, SG)                                       \
     do {                                                       \

@@ -12,7 +12,7 @@
 //       24     4  nodes                 28  4  longest pattern
 //       32     4  shortest pattern      36  4  merge levels of the table (pfac_build_ex)
 //       40     4  tuning: algo | span log2 << 8 | root depth << 16 | filter key << 24
-//       44     4  tuning: grid
+//       44     4  tuning: grid | positions per thread << 24 (lane bytes 16 or 32; 0 = 32)
 //       48     8  payload bytes
 //       56     8  FNV-1a 64 of bytes 0..55 and of the payload
 //
@@ -186,7 +186,7 @@ extern "C" int pfac_save(const pfac_automaton *a, uint8_t *buf, uint64_t cap, ui
     put<uint32_t>(buf, 36, a->merge_levels);
     put<uint32_t>(buf, 40, (a->algo & 0xff) | ((a->span_log2 & 0xff) << 8) | ((a->req_depth & 0xff) << 16) |
                                ((a->req_k & 0xff) << 24));
-    put<uint32_t>(buf, 44, a->grid);
+    put<uint32_t>(buf, 44, (a->grid & 0xffffffu) | ((a->lane_bytes & 0xffu) << 24));
     put<uint64_t>(buf, 48, z.total);
     uint64_t at = kHeader;
     memcpy(buf + at, a->pat_off.data(), z.pat_off);
@@ -270,7 +270,10 @@ extern "C" int pfac_load(const uint8_t *buf, uint64_t size, pfac_automaton **out
         a->span_log2 = (tune >> 8) & 0xff;
         a->req_depth = (tune >> 16) & 0xff;
         a->req_k = tune >> 24;
-        a->grid = grid;
+        a->grid = grid & 0xffffffu;
+        const uint32_t lb = grid >> 24;
+        if (lb != 0 && lb != 16 && lb != 32) throw 1;
+        a->lane_bytes = lb == 16 ? 16u : 32u;
         if (a->algo > PFAC_ALGO_TILED) throw 1;
         if (a->span_log2 && (a->span_log2 < pfac::kMinSpanLog2 || a->span_log2 > pfac::kMaxSpanLog2)) throw 1;
         if (n_pats) {

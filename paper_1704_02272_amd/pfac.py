@@ -95,10 +95,11 @@ ALGOS = {"auto": PFAC_ALGO_AUTO, "plain": PFAC_ALGO_PLAIN, "tiled": PFAC_ALGO_TI
 
 class Tuning(C.Structure):
     _fields_ = [("algo", C.c_uint32), ("grid", C.c_uint32), ("span_log2", C.c_uint32),
-                ("root_depth", C.c_uint32), ("filter_k", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("root_depth", C.c_uint32), ("filter_k", C.c_uint32), ("lane_bytes", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
 
 
-TUNING_FIELDS = ("algo", "grid", "span_log2", "root_depth", "filter_k")
+TUNING_FIELDS = ("algo", "grid", "span_log2", "root_depth", "filter_k", "lane_bytes")
 
 
 def lib():
@@ -270,8 +271,8 @@ def pfac_export_outputs(a: Automaton):
 
 
 def pfac_set_tuning(a: Automaton, algo: str = "auto", grid: int = 0, span_log2: int = 0,
-                    root_depth: int = 0, filter_k: int = 0):
-    t = Tuning(ALGOS[algo], grid, span_log2, root_depth, filter_k)
+                    root_depth: int = 0, filter_k: int = 0, lane_bytes: int = 0):
+    t = Tuning(ALGOS[algo], grid, span_log2, root_depth, filter_k, lane_bytes)
     _check(lib().pfac_set_tuning(a.handle, C.byref(t)), "pfac_set_tuning")
 
 

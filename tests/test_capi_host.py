@@ -185,9 +185,10 @@ def test_save_load_round_trip(k):
 def test_save_keeps_tuning():
     pats = [b"abcd", b"abce", b"xyzw", b"qq12"]
     a = pfac.pfac_build(pats, 256)
-    pfac.pfac_set_tuning(a, algo="tiled", grid=300, span_log2=13, root_depth=1, filter_k=3)
+    pfac.pfac_set_tuning(a, algo="tiled", grid=300, span_log2=13, root_depth=1, filter_k=3, lane_bytes=16)
     b = pfac.pfac_load(pfac.pfac_save(a))
     assert pfac.pfac_get_tuning(b) == pfac.pfac_get_tuning(a)
+    assert pfac.pfac_get_tuning(b)["lane_bytes"] == 16 and pfac.pfac_get_tuning(b)["grid"] == 300
     assert pfac.pfac_table_info(b)["root_depth"] == 1 and pfac.pfac_table_info(b)["filter_k"] == 3
 
 
@@ -302,11 +303,19 @@ def test_tuning_rebuilds_lds_image_on_host():
     # out of range: shorter than the root depth, longer than the shortest pattern allows,
     # a span outside 11..16; the previous tuning stays in force
     for bad in (dict(root_depth=1, filter_k=5), dict(root_depth=3), dict(root_depth=2, filter_k=1),
-                dict(span_log2=10), dict(span_log2=17)):
+                dict(span_log2=10), dict(span_log2=17), dict(lane_bytes=8), dict(lane_bytes=64),
+                dict(grid=1 << 24)):
         with pytest.raises(pfac.PfacError) as e:
             pfac.pfac_set_tuning(a, **bad)
         assert e.value.code == pfac.PFAC_EINVAL
         assert pfac.pfac_get_tuning(a) == t1
+    # positions per thread: 16 or 32 for the hashed form; the sampled form (the builder's
+    # choice here: bytes, no pattern shorter than 4) always takes 32
+    assert t1["lane_bytes"] == 32
+    pfac.pfac_set_tuning(a, span_log2=11, root_depth=1, filter_k=3, lane_bytes=16)
+    assert pfac.pfac_get_tuning(a)["lane_bytes"] == 16
+    pfac.pfac_set_tuning(a, lane_bytes=16)
+    assert pfac.pfac_get_tuning(a)["lane_bytes"] == 32
     # back to the builder's choice
     pfac.pfac_set_tuning(a)
     assert pfac.pfac_get_tuning(a) == t0
