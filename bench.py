@@ -125,6 +125,53 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def bench_launch(args, w):
+    """Eager launch pairs against replays of one captured graph of the same packet batch:
+    groups of --steps launches on one stream, alternating, each timed for the host's
+    enqueue (no synchronization inside the group) and in all (up to the synchronization
+    after it). Under a kernel trace the groups show where a replay's extra time goes."""
+    import numpy as np
+    import torch
+
+    import paper_1704_02272_amd.pfac as pfac
+
+    dev = torch.device("cuda:0")
+    n = int(w.offsets[-1])
+    a = pfac.pfac_build(w.patterns, w.alphabet)
+    pfac.pfac_set_tuning(a, span_log2=12, root_depth=1, filter_k=4)
+    d = torch.from_numpy(w.data).to(dev)
+    offs = torch.from_numpy(w.offsets.view(np.int64)).to(dev)
+    count = int(pfac.pfac_scan_batch(a, d, offs).numel())
+    keys = torch.empty(max(count, 1), dtype=torch.int64, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.Stream()
+    sizes = torch.tensor([n, w.n_packets], dtype=torch.int64, device=dev)
+    g = pfac.pfac_graph_create(a, d, offs, keys, cnt, sizes, stream)
+    launch = {"eager": lambda: pfac.pfac_scan_batch_async(a, d, offs, keys, cnt, stream),
+              "graph": lambda: g.launch(stream)}
+    res = {"eager": [], "graph": []}
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            for mode in ("eager", "graph"):
+                for _ in range(args.warmup):
+                    launch[mode]()
+                stream.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    launch[mode]()
+                t1 = time.perf_counter()
+                stream.synchronize()
+                t2 = time.perf_counter()
+                if int(cnt.item()) != count:
+                    raise RuntimeError("match count changed: %d vs %d" % (int(cnt.item()), count))
+                res[mode].append({"enqueue_us": round((t1 - t0) / args.steps * 1e6, 2),
+                                  "total_us": round((t2 - t0) / args.steps * 1e6, 2)})
+                time.sleep(0.01)  # a visible gap between the groups in a trace
+    g.close()
+    print(json.dumps({"mode": "launch", "workload": "packets_256", "bytes": n, "packets": w.n_packets,
+                      "matches": count, "launches_per_group": args.steps, **res}), flush=True)
+
+
 def bench_packets(args, w):
     """Packet batch: one persistent launch pair per batch (eager, and replayed from a
     captured graph) against one plain launch per packet, all on one stream."""
@@ -593,12 +640,14 @@ def main():
     ap.add_argument("--sweep-files", type=int, default=5, help="sweep: seeded texts per alphabet")
     ap.add_argument("--baseline-steps", type=int, default=3,
                     help="packets: timed passes of the per-packet baseline")
-    ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host", "sizes", "sweep", "prefix"],
+    ap.add_argument("--mode", default="scan", choices=["scan", "copy", "host", "sizes", "sweep", "prefix", "launch"],
                     help="copy: a plain device-to-device copy of the workload's text, the "
                          "reference that scales the HBM byte counters of the scan; host: the "
                          "text starts in host memory (pinned, then pageable) and crosses PCIe "
                          "inside the timed region; sizes: the trie-size study of Section 4.1 (no GPU); "
-                         "sweep: throughput over alphabets and pattern counts (Section 4.3)")
+                         "sweep: throughput over alphabets and pattern counts (Section 4.3); "
+                         "launch (packets_256): eager launch pairs against graph replays of one "
+                         "batch, host enqueue time and total time per launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -626,7 +675,10 @@ def main():
         return
     w = make_workload(args.workload)
     if args.workload == "packets_256":
-        bench_packets(args, w)
+        if args.mode == "launch":
+            bench_launch(args, w)
+        else:
+            bench_packets(args, w)
         return
     n = len(w.text)
     a = pfac.pfac_build(w.patterns, w.alphabet)

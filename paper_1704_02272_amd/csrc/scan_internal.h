@@ -59,6 +59,10 @@ constexpr uint32_t kRecRounds = 4;   // 64-record rounds whose loads a placement
 #endif
 constexpr uint32_t kPlaceThreads = PFAC_PLACE_THREADS;  // placement workgroup (its waves share a block's spans)
 constexpr uint32_t kPlaceWaves = kPlaceThreads / 64;
+#ifndef PFAC_PLACE_SUM_LOADS
+#define PFAC_PLACE_SUM_LOADS (4096 / PFAC_PLACE_THREADS)
+#endif
+constexpr uint32_t kSumLoads = PFAC_PLACE_SUM_LOADS;  // loads in flight per thread in a block's span-count sum
 
 // LDS of the scan kernel (32-bit words), one of two layouts per kernel instance (a
 // probe's masked hash plus its part's compile-time offset is its byte address; every

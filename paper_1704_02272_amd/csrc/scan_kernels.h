@@ -1195,15 +1195,15 @@ __global__ __launch_bounds__(kPlaceThreads) void place_emit(DevTable t, const ui
         if (direct) {
             uint64_t part = 0;
             const uint32_t lim_s = blk * kBlockSpans;
-            for (uint32_t s0 = 0; s0 < lim_s; s0 += 16 * kPlaceThreads) {
-                uint64_t v[16];
+            for (uint32_t s0 = 0; s0 < lim_s; s0 += kSumLoads * kPlaceThreads) {
+                uint64_t v[kSumLoads];
 #pragma unroll
-                for (uint32_t u = 0; u < 16; u++) {
+                for (uint32_t u = 0; u < kSumLoads; u++) {
                     const uint32_t s = s0 + u * kPlaceThreads + threadIdx.x;
                     v[u] = so.cnt[s < lim_s ? s : 0u];
                 }
 #pragma unroll
-                for (uint32_t u = 0; u < 16; u++) part += s0 + u * kPlaceThreads + threadIdx.x < lim_s ? v[u] : 0u;
+                for (uint32_t u = 0; u < kSumLoads; u++) part += s0 + u * kPlaceThreads + threadIdx.x < lim_s ? v[u] : 0u;
             }
             part = wave_sum64(part);
             if (lane == 0) pre[wave] = part;
