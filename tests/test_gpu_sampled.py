@@ -1,6 +1,7 @@
 """GPU parity of the sampled prefilter form: byte patterns of four or more bytes with a
 4-byte filter key, where only every second start is probed (with its 3-gram) and each
-lane then checks the 4-grams of its own candidates from its registers. The edge cases of
+lane then checks the 4-grams of its own candidates, reading their bytes back from its
+copy of the step's bytes in LDS. The edge cases of
 that path, each compared element by element with the oracle: texts shorter than a step,
 ragged ends, several span lengths, texts that do not start on a 16-byte boundary (the
 guarded loads), matches across lane, step and span boundaries, lanes with many
