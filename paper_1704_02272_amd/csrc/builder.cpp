@@ -300,6 +300,7 @@ void finish_automaton(pfac_automaton *a) {
     std::vector<uint8_t> dtail;
     a->dev_out_first.clear();
     a->dev_out_ids.clear();
+    a->dev_tail_head.clear();  // plain table only (below)
     if (a->merge_levels) {
         const uint32_t R = a->n_rec;
         dfirst = a->rec_first;
@@ -367,6 +368,13 @@ void finish_automaton(pfac_automaton *a) {
             if (tails[(size_t)i * 4 + 3] == 1) tails[(size_t)i * 4 + 2] = a->dev_out_ids.back();  // the id itself
         }
         a->dev_tails.swap(tails);
+        // the first kHeadBytes bytes of every record's path, beside the records
+        a->dev_tail_head.assign((size_t)heads.size() * kHeadBytes, 0);
+        for (uint32_t i = 0; i < heads.size(); i++) {
+            const uint32_t off = a->dev_tails[(size_t)i * 4 + 0], len = a->dev_tails[(size_t)i * 4 + 1];
+            const uint32_t h = len < kHeadBytes ? len : kHeadBytes;
+            if (h) memcpy(&a->dev_tail_head[(size_t)i * kHeadBytes], &a->pat_bytes[off], h);
+        }
     }
     const uint32_t R = (uint32_t)dord.size();
     a->dev_records = R;

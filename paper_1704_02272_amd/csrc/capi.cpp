@@ -83,8 +83,8 @@ extern "C" void pfac_destroy(pfac_automaton *a) { delete a; }
 // Every byte a device copy of the automaton holds in HBM (as the runtime uploads it).
 static uint64_t device_bytes(const pfac_automaton *a) {
     uint64_t b = a->dev_nodes.size() * 8 + a->dev_bm.size() * 8 + a->dev_tails.size() * 4 +
-                 a->pat_bytes.size() + a->lds_image.size() * 4 + a->dev_out_first.size() * 4 +
-                 a->dev_out_ids.size() * 4;
+                 a->dev_tail_head.size() + a->pat_bytes.size() + a->lds_image.size() * 4 +
+                 a->dev_out_first.size() * 4 + a->dev_out_ids.size() * 4;
     if (a->merge_levels) b += a->rec_rank.size() * 4;
     return b;
 }

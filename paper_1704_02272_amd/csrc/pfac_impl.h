@@ -41,6 +41,7 @@ constexpr uint32_t kNarrowIndexMask = 0x3fffffffu;  // NARROW: first child / tai
 constexpr uint64_t kOneIdBit = 1ull << 4;
 constexpr uint32_t kOneIdShift = 5;
 constexpr uint32_t kOneIdMax = 1u << 27;
+constexpr uint32_t kHeadBytes = 16;  // path bytes kept beside each tail record (plain table)
 constexpr uint32_t kMaxPatternLen = 1u << 24;
 constexpr uint32_t kMaxNodes = 0x7fffffffu;
 constexpr uint32_t kMaxMergeLevels = 255;  // levels >= the deepest height merge everything
@@ -71,6 +72,10 @@ struct DevTable {
     // not stored.
     const uint32_t *tails;
     const uint8_t *tail_bytes;
+    // Plain table: the first kHeadBytes bytes of each tail record's path (zero past its
+    // length), kHeadBytes per record in record order, so a walk loads them together with
+    // the record. Null for a compressed table.
+    const uint4 *tail_head;
     uint32_t alphabet;
     uint32_t layout;            // Layout
     uint32_t nw_log2;           // WIDE: log2(NW)
@@ -144,7 +149,7 @@ struct DeviceCopy {
     int device = -1;
     uint32_t cus = 256;  // compute units of the device
     void *nodes = nullptr, *bm = nullptr, *out_first = nullptr, *out_ids = nullptr,
-         *lds_image = nullptr, *tails = nullptr, *tail_bytes = nullptr, *rk = nullptr;
+         *lds_image = nullptr, *tails = nullptr, *tail_bytes = nullptr, *rk = nullptr, *tail_head = nullptr;
     DevTable view{};
     std::map<void *, Workspace *> workspaces;  // keyed by stream
     // LDS images replaced by a change of tuning. Queued scans and captured graphs may
@@ -186,6 +191,7 @@ struct pfac_automaton {
     std::vector<uint64_t> dev_nodes, dev_bm;
     std::vector<uint32_t> lds_image;
     std::vector<uint32_t> dev_tails;  // see DevTable::tails
+    std::vector<uint8_t> dev_tail_head;  // see DevTable::tail_head
     std::vector<uint32_t> dev_out_first, dev_out_ids;  // ids as the device table indexes them
     uint32_t dev_records = 0;         // records of the device table
     pfac::DevTable shape{};  // pointer fields null; filled per device copy

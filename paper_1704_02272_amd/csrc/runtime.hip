@@ -117,6 +117,7 @@ void free_copy(DeviceCopy *c) {
     hipFree(c->lds_image);
     hipFree(c->tails);
     hipFree(c->tail_bytes);
+    hipFree(c->tail_head);
     hipFree(c->rk);
     for (void *p : c->retired) hipFree(p);
     hipSetDevice(prev);
@@ -217,6 +218,7 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     if (!rc) rc = upload_vec(a->lds_image, &c->lds_image);
     if (!rc) rc = upload_vec(a->dev_tails, &c->tails);
     if (!rc) rc = upload_vec(a->pat_bytes, &c->tail_bytes);
+    if (!rc) rc = upload_vec(a->dev_tail_head, &c->tail_head);
     if (rc) {
         free_copy(c);
         return rc;
@@ -229,6 +231,7 @@ static int get_copy(pfac_automaton *a, DeviceCopy **out) {
     c->view.lds_image = (const uint32_t *)c->lds_image;
     c->view.tails = (const uint32_t *)c->tails;
     c->view.tail_bytes = (const uint8_t *)c->tail_bytes;
+    c->view.tail_head = (const uint4 *)c->tail_head;
     c->view.rk = (const uint32_t *)c->rk;
     // set-up of pfac_scan_noalloc on this device (its scratch array's device address);
     // a failure here is reported by that call, which tries again
@@ -599,6 +602,7 @@ static int reupload_lds_images(pfac_automaton *a) {
         v.out_ids = c->view.out_ids;
         v.tails = c->view.tails;
         v.tail_bytes = c->view.tail_bytes;
+        v.tail_head = c->view.tail_head;
         v.rk = c->view.rk;
         v.lds_image = (const uint32_t *)c->lds_image;
         c->view = v;

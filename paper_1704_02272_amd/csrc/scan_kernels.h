@@ -181,10 +181,8 @@ struct Trie {
             return (int64_t)(r + __builtin_popcountll(word & ((1ull << b) - 1ull)));
         }
     }
-    // Plain table: tail record {offset in tail_bytes, length, first id index, id count}.
-    __device__ __forceinline__ uint4 tail_rec(uint64_t w) const {
-        return reinterpret_cast<const uint4 *>(t.tails)[w_index(w)];
-    }
+    // Plain table: tail records {offset in tail_bytes, length, first id index, id count},
+    // read by tail_match.
 
     // Plain table: ids of terminal q (word w): the count, and the first id (one = true:
     // read from the word) or the index of the ids in out_ids.
@@ -238,6 +236,41 @@ struct Trie {
         return true;
     }
 
+    // Plain table, at the tail head whose word is w and text position i (end exclusive):
+    // whether the text from i spells the head's path, with its record in tr. The record,
+    // the copy of the path's first kHeadBytes bytes kept beside it and the text dwords
+    // those bytes cover (never past end) are all loaded before any compare, so the walk
+    // pays one memory round trip here; a longer path compares the rest after.
+    __device__ __forceinline__ bool tail_match(uint64_t w, const uint8_t *__restrict__ text, uint64_t i,
+                                               uint64_t end, uint4 &tr) const {
+        static_assert(kHeadBytes == 16, "one 16-byte load of path bytes");
+        const uint32_t x = w_index(w);
+        tr = reinterpret_cast<const uint4 *>(t.tails)[x];
+        const uint4 h0 = t.tail_head[x];
+        const uint64_t lim = i + kHeadBytes < end ? i + kHeadBytes : end;
+        const uintptr_t ta = (uintptr_t)(text + i);
+        const uint32_t *tw = reinterpret_cast<const uint32_t *>(ta & ~(uintptr_t)3);
+        const uint32_t ts = (uint32_t)(ta & 3);
+        const uint32_t nt = (uint32_t)((ts + (lim - i) + 3) >> 2);  // dwords holding text bytes below lim
+        uint32_t xw[kHeadBytes / 4 + 1];
+#pragma unroll
+        for (uint32_t k = 0; k <= kHeadBytes / 4; k++) xw[k] = k < nt ? tw[k] : 0u;
+        if (i + tr.y > end) return false;
+        const uint32_t len = tr.y, hl = len < kHeadBytes ? len : kHeadBytes;
+        const uint32_t pw[kHeadBytes / 4] = {h0.x, h0.y, h0.z, h0.w};
+        uint32_t diff = 0;
+#pragma unroll
+        for (uint32_t g = 0; g < kHeadBytes / 4; g++) {
+            const uint32_t b = 4 * g;  // first compared byte of this group
+            if (b < hl) {
+                const uint32_t m = b + 4 <= hl ? 0xffffffffu : (1u << (8 * (hl - b))) - 1u;
+                diff |= (__builtin_amdgcn_alignbyte(xw[g + 1], xw[g], ts) ^ pw[g]) & m;
+            }
+        }
+        if (diff) return false;
+        return len <= kHeadBytes || tail_equal(text, i + kHeadBytes, tr.x + kHeadBytes, len - kHeadBytes);
+    }
+
     // One move of a walk at node q, text position i < end: the next symbol by Eq. 1, and
     // when q has a path tail and that symbol starts it, the rest of the tail at once. A
     // mismatch on the first symbol thus costs no more than a plain step. False when the
@@ -287,8 +320,8 @@ struct Trie {
                 }
                 if (i >= end) break;
                 if (w_tail(w)) {
-                    const uint4 tr = tail_rec(w);
-                    if (i + tr.y <= end && tail_equal(text, i, tr.x, tr.y)) {
+                    uint4 tr;
+                    if (tail_match(w, text, i, end, tr)) {
                         r.cnt += tr.w;
                         if (r.nterm == 0) {
                             r.f0 = tr.z;
@@ -349,8 +382,8 @@ struct Trie {
                 }
                 if (i >= end) break;
                 if (w_tail(w)) {
-                    const uint4 tr = tail_rec(w);
-                    if (i + tr.y <= end && tail_equal(text, i, tr.x, tr.y)) {
+                    uint4 tr;
+                    if (tail_match(w, text, i, end, tr)) {
                         nterm++;
                         if (tr.w == 1) keys[o + k++] = hi | tr.z;  // the id itself
                         else
@@ -459,8 +492,8 @@ struct RootWalk {
                 }
                 if (i >= end) break;
                 if (T.w_tail(w)) {
-                    const uint4 tr = T.tail_rec(w);
-                    if (i + tr.y <= end && T.tail_equal(text, i, tr.x, tr.y))
+                    uint4 tr;
+                    if (T.tail_match(w, text, i, end, tr))
                         note(tr.z, tr.w, tr.w == 1, kNone, (uint32_t)(i - s) + tr.y);
                     break;
                 }
