@@ -449,10 +449,18 @@ struct RootWalk {
                 if (s + i < end) w8 |= (uint64_t)text[s + i] << (8 * i);
         }
         uint32_t key = 0;
-        for (uint32_t i = 0; i < D; i++) {
-            const uint32_t c = (uint32_t)(w8 >> (8 * i)) & 0xffu;
-            if (PACK2 && c > 3) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};  // a byte outside the 2-bit codes
-            key = (key << (PACK2 ? 2 : 8)) | c;
+        if constexpr (PACK2) {
+            // the first D bytes (D <= 8) must all be 2-bit codes; the key packs them two
+            // bits each, the first symbol highest, with word-wide operations
+            const uint64_t dm = D >= 8 ? ~0ull : (1ull << (8 * D)) - 1ull;
+            if (w8 & dm & 0xfcfcfcfcfcfcfcfcull) return WalkResult{0, 0, 0, 0, 0, 0, 0, 0, 0};
+            auto code4 = [](uint32_t x) {  // bytes b0..b3 (each < 4) -> b0 b1 b2 b3, two bits each
+                return ((x & 0xffu) << 6) | ((x >> 4) & 0x30u) | ((x >> 14) & 0x0cu) | (x >> 24);
+            };
+            const uint32_t c8 = (code4((uint32_t)(w8 & dm)) << 8) | code4((uint32_t)((w8 & dm) >> 32));
+            key = c8 >> (2 * (8 - D));
+        } else {
+            for (uint32_t i = 0; i < D; i++) key = (key << 8) | ((uint32_t)(w8 >> (8 * i)) & 0xffu);
         }
         const uint32_t wi = key >> 5, b = key & 31;
         const uint32_t word = img[Lds<FORM>::root + wi];
