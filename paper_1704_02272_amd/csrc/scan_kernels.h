@@ -577,15 +577,19 @@ __device__ __forceinline__ uint4 load16(const uint8_t *__restrict__ text, uint64
 
 // Two-bit codes of 16 bytes, first byte in the top bits.
 __device__ __forceinline__ uint32_t pack2x16(uint4 v) {
-    uint32_t d[4] = {v.x, v.y, v.z, v.w};
-    uint32_t c = 0;
+    // Per dword, bytes b0..b3 keep their low two bits (y). One 24-bit multiply-add puts
+    // b0 b1 b2 b3 (two bits each, b0 highest) in byte 2 of p: y's low three bytes times
+    // 2^22 + 2^12 + 2^2 land b0, b1, b2 at bits 22, 20, 18 (the other partial products
+    // stay below bit 14 or start at bit 28), and the added byte-permute of y puts b3 at
+    // bit 16. Two permutes and an or then gather the four code bytes, first dword highest.
+    const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+    uint32_t p[4];
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-        uint32_t y = d[i] & 0x03030303u;
-        uint32_t code = ((y & 0xffu) << 6) | ((y >> 4) & 0x30u) | ((y >> 14) & 0x0cu) | (y >> 24);
-        c = (c << 8) | code;
+        const uint32_t y = d[i] & 0x03030303u;
+        p[i] = __umul24(y, 0x401004u) + __builtin_amdgcn_perm(y, y, 0x0c030c0cu);  // low 24 bits of y
     }
-    return c;
+    return __builtin_amdgcn_perm(p[0], p[1], 0x06020c0cu) | __builtin_amdgcn_perm(p[2], p[3], 0x0c0c0602u);
 }
 
 // First prefilter probe of a key: the word at the masked high half of key * kFilterMul
