@@ -970,9 +970,9 @@ struct Scanner {
 
     // One step's prefilter mask: candidates (sampled prefilter, checked here) or survivors.
     __device__ __forceinline__ void step_body(SpanState &S, uint64_t step, uint64_t top, const Chunk &cur, uint32_t nd,
-                                              uint32_t nc) {
+                                              uint32_t nc, uint32_t pc) {
         uint32_t sl0;
-        const uint32_t m = mask_step(S, step, top, cur, nd, nc, &sl0);
+        const uint32_t m = mask_step(S, step, top, cur, nd, nc, pc, &sl0);
         if constexpr (kSampled)
             sample_step(S, step, cur, nd, m, sl0);
         else
@@ -994,16 +994,18 @@ struct Scanner {
 
     // Survivor mask of this lane's kLB starts at `step` (bit j = start
     // step + kLB * lane + j), cut to [S.a, top). next_d0 / next_c: first word / first
-    // two-bit codes of the bytes after this lane's.
+    // two-bit codes of the bytes after this lane's; pc: two-bit codes of the lane's first
+    // 16 bytes.
     __device__ __forceinline__ uint32_t mask_step(const SpanState &S, uint64_t step, uint64_t top, const Chunk &cur,
-                                                  uint32_t next_d0, uint32_t next_c, uint32_t *sl0_out) const {
+                                                  uint32_t next_d0, uint32_t next_c, uint32_t pc,
+                                                  uint32_t *sl0_out) const {
         const uint32_t lane = lane_id();
         uint32_t m = 0;
 #pragma unroll
         for (uint32_t h = 0; h < kLB / 16; h++) {
             const bool lasth = h + 1 == kLB / 16;
             const uint32_t nd = lasth ? next_d0 : cur.v[h + 1].x;
-            const uint32_t c0 = PACK2 ? pack2x16(cur.v[h]) : 0u;
+            const uint32_t c0 = PACK2 ? (h == 0 ? pc : pack2x16(cur.v[h])) : 0u;
             const uint32_t c1 = PACK2 ? (lasth ? next_c : pack2x16(cur.v[h + 1])) : 0u;
             m |= prefilter16<PACK2, FM>(t, W.img, cur.v[h], nd, c0, c1) << (16 * h);
         }
@@ -1020,16 +1022,17 @@ struct Scanner {
     }
 
     // First word and first two-bit codes of the next lane's chunk (the last lane takes
-    // them from the next step's lane 0, or from `after` past the span's last step).
+    // them from the next step's lane 0, or from `after` past the span's last step). pc /
+    // pn: two-bit codes of the first 16 bytes of this lane's chunk and of its next step's.
     __device__ __forceinline__ void next_lane_head(const Chunk &cur, const Chunk &nxt, bool last, uint4 after,
-                                                   uint32_t *d0, uint32_t *c0) const {
+                                                   uint32_t pc, uint32_t pn, uint32_t *d0, uint32_t *c0) const {
         const uint32_t lane = lane_id();
         const uint32_t dn = from_next_lane(cur.v[0].x);
         const uint32_t d0n = last ? after.x : __builtin_amdgcn_readfirstlane(nxt.v[0].x);
         *d0 = lane == 63 ? d0n : dn;
         if (PACK2) {
-            const uint32_t cn = from_next_lane(pack2x16(cur.v[0]));
-            const uint32_t c0n = last ? pack2x16(after) : __builtin_amdgcn_readfirstlane(pack2x16(nxt.v[0]));
+            const uint32_t cn = from_next_lane(pc);
+            const uint32_t c0n = last ? pack2x16(after) : __builtin_amdgcn_readfirstlane(pn);
             *c0 = lane == 63 ? c0n : cn;
         } else {
             *c0 = 0;
@@ -1057,6 +1060,9 @@ struct Scanner {
             for (uint32_t i = 0; i < kPf; i++)
                 buf[i] = chunk_buffer(rs, loff, (uint32_t)(step + i * kSt < lastst ? step + i * kSt : lastst));
             const uint32_t last32 = (uint32_t)lastst;  // the text is below 4 GiB
+            // two-bit codes of the first 16 bytes of this step's chunk, carried over from
+            // the step before (it needs the next step's for its last lane)
+            uint32_t pc = PACK2 ? pack2x16(buf[0].v[0]) : 0u;
             for (; step < hiR; step += kSt) {
                 // kPf steps ahead, clamped to the last step (32-bit scalar arithmetic;
                 // step <= lastst here, so the difference does not wrap)
@@ -1064,8 +1070,10 @@ struct Scanner {
                 const uint32_t ak = last32 - st32 > kPf * kSt ? st32 + kPf * kSt : last32;
                 const Chunk nxk = chunk_buffer(rs, loff, ak);
                 uint32_t nd, nc;
-                next_lane_head(buf[0], buf[1 % kPf], step == lastst, after, &nd, &nc);
-                step_body(S, step, top, buf[0], nd, nc);
+                const uint32_t pn = PACK2 ? pack2x16(buf[1 % kPf].v[0]) : 0u;
+                next_lane_head(buf[0], buf[1 % kPf], step == lastst, after, pc, pn, &nd, &nc);
+                step_body(S, step, top, buf[0], nd, nc, pc);
+                pc = pn;
 #pragma unroll
                 for (uint32_t i = 0; i + 1 < kPf; i++) buf[i] = buf[i + 1];
                 buf[kPf - 1] = nxk;
@@ -1079,8 +1087,9 @@ struct Scanner {
             for (; step < hi; step += kSt) {
                 const Chunk nx2 = chunk_guarded(step + 2 * kSt + kLB * lane, ld);
                 uint32_t nd, nc;
-                next_lane_head(cur, nx1, false, make_uint4(0u, 0u, 0u, 0u), &nd, &nc);
-                step_body(S, step, top, cur, nd, nc);
+                const uint32_t pc = PACK2 ? pack2x16(cur.v[0]) : 0u, pn = PACK2 ? pack2x16(nx1.v[0]) : 0u;
+                next_lane_head(cur, nx1, false, make_uint4(0u, 0u, 0u, 0u), pc, pn, &nd, &nc);
+                step_body(S, step, top, cur, nd, nc, pc);
                 cur = nx1;
                 nx1 = nx2;
             }
