@@ -622,6 +622,8 @@ def main():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--lane-bytes", type=int, default=0, choices=[0, 16, 32],
                     help="scan: positions per thread and step (0: the library's default)")
+    ap.add_argument("--span-log2", type=int, default=0,
+                    help="scan: log2 of the span length, 11..16 (0: chosen from the text size)")
     ap.add_argument("--streams", type=int, default=1, help="scan: streams the scans alternate over")
     ap.add_argument("--no-pipelined", dest="pipelined", action="store_false",
                     help="scan: skip the extra two-stream measurement")
@@ -683,8 +685,8 @@ def main():
     n = len(w.text)
     a = pfac.pfac_build(w.patterns, w.alphabet)
     info = pfac.pfac_table_info(a)
-    if args.algo != "auto" or args.lane_bytes:
-        pfac.pfac_set_tuning(a, algo=args.algo, lane_bytes=args.lane_bytes)
+    if args.algo != "auto" or args.lane_bytes or args.span_log2:
+        pfac.pfac_set_tuning(a, algo=args.algo, lane_bytes=args.lane_bytes, span_log2=args.span_log2)
     if args.mode == "host":
         pinned = torch.empty(n, dtype=torch.uint8, pin_memory=True)
         pinned.numpy()[:] = w.text
