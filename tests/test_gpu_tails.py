@@ -5,7 +5,8 @@ compared key for key with the oracle: paths that start right at the root image's
 and deeper, texts ending inside a path or one symbol short of its end, a mismatch at the
 path's last symbol, duplicate patterns at a path's end, a pattern that is a prefix of a
 longer one (a terminal above the path), bytes outside the alphabet, packet ends inside a
-path; for the tiled scan, the plain baseline and the prefix depths."""
+path; tail lengths around the 16 path bytes kept beside each record; for the tiled scan,
+the plain baseline and the prefix depths."""
 import numpy as np
 import pytest
 
@@ -102,3 +103,35 @@ def test_paths_at_every_depth_and_packet_ends():
     got = pfac.keys_to_numpy(pfac.pfac_scan_batch(a, data, offs))
     torch.cuda.synchronize()
     assert np.array_equal(got, ac.scan_packets(text, cuts))
+
+
+@pytest.mark.parametrize("alphabet", [4, 256])
+def test_tail_lengths_around_the_copied_path_bytes(alphabet):
+    """A walk at a tail head compares the first 16 bytes of the path from a copy kept
+    beside the record and the rest from the pattern bytes: tails of 15 to 17 and 31 to
+    33 bytes, mismatches at the first, 16th, 17th and last tail byte, and texts that end
+    0 to 3 bytes short of a whole match, with 16 and 32 starts a lane."""
+    rng = np.random.default_rng(31 + alphabet)
+    head = 8 if alphabet == 4 else 2  # the root image's depth: tails start below it
+    pats = []
+    for i, tl in enumerate((1, 8, 15, 16, 17, 31, 32, 33, 47)):
+        lead = [(i >> (2 * k)) & 3 for k in range(head)] if alphabet == 4 else [65 + i, 66]
+        body = rng.integers(0, alphabet, size=tl).astype(np.uint8)
+        pats.append(bytes(lead) + bytes(body))
+    pieces = []
+    for p in pats:
+        for k in (None, head, head + 15, head + 16, len(p) - 1):
+            q = bytearray(p)
+            if k is not None and k < len(q):
+                q[k] = (q[k] + 1) % alphabet
+            pieces.append(bytes(q))
+    sep = bytes([3, 2, 1, 0, 3, 3]) if alphabet == 4 else b"#~"
+    body = sep.join(pieces) + sep
+    ac = native.AhoCorasick(pats, alphabet)
+    a = pfac.pfac_build(pats, alphabet)
+    for lb in (16, 32):
+        pfac.pfac_set_tuning(a, lane_bytes=lb)
+        for p in pats:
+            for cut in range(4):
+                text = np.frombuffer(body + p[: len(p) - cut], np.uint8).copy()
+                assert np.array_equal(_keys(a, text), ac.scan(text)), (alphabet, lb, len(p), cut)
