@@ -120,8 +120,9 @@ typedef struct {
     uint32_t node_layout;        /* 0: 8-byte node (alphabet <= 32), 1: wide node      */
     uint64_t paper_table_bytes;  /* n_nodes * (4 + ceil(alphabet / 8)), Section 3.1    */
     uint64_t device_table_bytes; /* everything a device copy holds in HBM: node arrays,
-                                    pattern ids (and rank words), path tails, pattern
-                                    bytes, LDS image source                             */
+                                    pattern ids (and rank words), path tails with the
+                                    first 16 bytes of each path, pattern bytes, LDS
+                                    image source                                        */
     uint32_t root_depth;         /* levels folded into the LDS-resident root image     */
     uint32_t filter_k;           /* symbols in the LDS prefix filter key (0 = none)    */
     uint32_t filter_log2_bits;   /* log2 of the filter's bit count (0 = none)          */
